@@ -1,0 +1,1 @@
+from .grid_ls import GridProblem, grid_ls, config_problem, batch_problem, batch_sides, default_depth, CONFIGS  # noqa: F401
