@@ -1,0 +1,175 @@
+/*
+ * spaqr.h — C-ABI of the MI355X spaQR least-squares library (libspaqr.so).
+ *
+ * Method: Gnanasekaran & Darve, "Hierarchical Orthogonal Factorization:
+ * Sparse Least Squares problems" (arXiv 2102.09878).  The library computes
+ * an approximate factorization Q^T (A D^-1) W^-1 ~ I of a tall sparse
+ * matrix A (M x N, M >= N, full column rank; Section 1, eq. (1.1)) by the
+ * level-by-level algorithm of Section 2 (Algorithm 1), and uses D^-1 W^-1 as
+ * a right preconditioner inside CGLS (Section 4).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns an int status: SPAQR_OK (0), a negative error code,
+ *    or SPAQR_NOCONV (+1, CGLS reached max_iter; the result is still
+ *    written).  No C++ exception crosses this boundary.  After an error,
+ *    spaqr_last_error(h) returns a message owned by the handle (or by the
+ *    library for calls that failed before a handle existed, h == NULL).
+ *  - The caller owns every buffer it passes.  The library copies what it
+ *    keeps; inputs may be freed as soon as a call returns.
+ *  - The handle owns all device memory of the plan and of the factors.
+ *  - "dev" pointers are device (GPU) pointers, e.g. torch.Tensor.data_ptr();
+ *    work on them is ordered on the handle's HIP stream (opt->stream, NULL
+ *    for the default stream).  Calls return after that work completed.
+ *  - CSR input: int64 row_ptr (M+1), int32 col_idx sorted and unique within
+ *    each row, double vals; every column must hold a nonzero.
+ *  - Columns are ordered by the analysis; "slots" below are column
+ *    positions 0..N-1 in which the factor W acts.
+ */
+#ifndef SPAQR_H
+#define SPAQR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPAQR_OK 0
+#define SPAQR_NOCONV 1
+#define SPAQR_EARG (-1)    /* invalid argument or malformed input           */
+#define SPAQR_ESTATE (-2)  /* call order violated (e.g. cgls before factor) */
+#define SPAQR_ERANK (-3)   /* a scaling block is numerically rank deficient */
+#define SPAQR_EHIP (-4)    /* HIP runtime error (no GPU, launch failure)    */
+#define SPAQR_ENOMEM (-5)  /* device or host allocation failed              */
+
+#define SPAQR_FP64 0          /* fronts and factors in FP64                  */
+#define SPAQR_FP32_FACTOR 1   /* fronts and factors in FP32; rank decisions,  */
+                              /* apply accumulation and CGLS in FP64          */
+
+#define SPAQR_WINV 0   /* out = W^-1 in  (slot space)  */
+#define SPAQR_WINVT 1  /* out = W^-T in  (slot space)  */
+
+typedef struct spaqr_handle_s* spaqr_handle;
+
+typedef struct {
+  int32_t nd_depth;      /* tree levels including the leaves; 0 => ceil(log2(N/64)) (Section 4) */
+  int32_t sparsify_skip; /* leaf-side levels left unsparsified; -1 => 2 (1 when depth <= 4)      */
+  int32_t grid[3];       /* nx, ny, nz of the cell grid (x fastest), nz = 1 in 2D; column j is   */
+                         /* cell j.  Geometric partitioning needs the grid (Section 4.1).        */
+  int32_t sep_width;     /* separator thickness in cell planes; 0 => 2                           */
+  int32_t precision;     /* SPAQR_FP64 or SPAQR_FP32_FACTOR                                      */
+  int32_t device;        /* HIP device ordinal                                                   */
+  void* stream;          /* hipStream_t, NULL => default stream                                  */
+} spaqr_options;
+
+typedef struct {
+  int32_t iters;           /* CGLS iterations taken                                          */
+  int32_t converged;       /* 1 if the stopping test held                                    */
+  double residual;         /* ||A^T (b - A x)|| / (||A||_2 ||b||), recomputed from x at exit */
+  double paper_residual;   /* ||A^T (A x - b)|| / ||A^T b|| (Section 4)                      */
+  double norm_a;           /* the ||A||_2 estimate used (30 power steps on A^T A from ones) */
+  double seconds;          /* wall time of the call                                          */
+} spaqr_cgls_info;
+
+typedef struct {
+  int32_t levels;            /* tree depth d                                        */
+  int32_t num_ops;           /* elementary ops of W                                 */
+  int32_t num_ranks;         /* rank decisions made (step 1 and step 2)             */
+  int32_t top_cols;          /* columns of the root cluster when it was eliminated  */
+  int32_t top_rows;          /* rows of the root cluster when it was eliminated     */
+  int32_t launches;          /* kernel launches of the last factorization           */
+  int32_t syncs;             /* host synchronisations of the last factorization     */
+  int32_t pad_;
+  int64_t mem_factor;        /* stored factor entries (mem_F of Table 1)            */
+  int64_t device_bytes;      /* device bytes held by the handle                     */
+  double flops[5];           /* algorithmic flops per phase: eliminate, reassign,   */
+  double bytes[5];           /* scale, sparsify, merge; and bytes moved per phase   */
+  double phase_seconds[5];   /* wall time per phase of the last factorization       */
+  double factor_seconds;     /* wall time of the last factorization                 */
+} spaqr_stats;
+
+typedef struct {
+  int32_t kind;   /* 0 eliminate (R_ss, R_sN), 1 scale (R_pp), 2 sparsify (Q_pp reflectors) */
+  int32_t n1;     /* eliminate: c_s;  scale: c_p;  sparsify: c_p                          */
+  int32_t n2;     /* eliminate: c_N;  scale: 0;    sparsify: rank r (reflector count)      */
+  int32_t round;  /* level-local round the op was created in                              */
+  int32_t level;  /* tree level being processed when the op was created                   */
+} spaqr_op_desc;
+
+/* Analysis (host only, no GPU needed): column scaling D (Section 2.7),
+ * geometric nested dissection with interfaces and their hierarchy
+ * (Section 2.2, Figure 3), row matching (column j <-> row j, the Laplacian
+ * row of cell j) and max-norm assignment of the other rows (Section 2.2),
+ * and the ||A||_2 estimate of the CGLS stopping test.
+ * Errors: SPAQR_EARG for M < N, N < 1, a malformed CSR, an empty column, a
+ * grid that does not match N or is too small for the depth, or a row that
+ * couples two sibling subtrees.  On success *out owns a new handle. */
+int spaqr_analyze(const int64_t* row_ptr, const int32_t* col_idx, const double* vals, int64_t M,
+                  int64_t N, const spaqr_options* opt, spaqr_handle* out);
+
+/* Column order and row owners chosen by the analysis (host buffers):
+ * col_perm[N] lists the columns cluster by cluster (finest clusters in
+ * elimination order, cells ascending); row_owner[M] is the finest-cluster
+ * index owning each row.  Either pointer may be NULL. */
+int spaqr_get_ordering(spaqr_handle h, int32_t* col_perm, int32_t* row_owner);
+
+/* Replace the nonzero values (same pattern) from a device buffer of nnz
+ * doubles; the analysis (ordering, owners) is kept, column norms are
+ * recomputed.  Any factor is invalidated. */
+int spaqr_set_values(spaqr_handle h, const double* vals_dev);
+
+/* Numeric factorization with tolerance eps >= 0 (Algorithm 1).  Ranks of
+ * the rank-revealing QRs follow |R_ii| >= eps |R_11| (Section 4).  Returns
+ * SPAQR_ERANK if a scaling block has |R_ii| <= 64 u ||A_pp||_F. */
+int spaqr_factorize(spaqr_handle h, double eps);
+
+/* Same, but every rank decision takes the next entry of ranks[nranks]
+ * (host buffer, in decision order: per level, step 1 over interfaces then
+ * step 2 round by round).  Used to compare factors with another
+ * implementation that chose these ranks.  SPAQR_EARG if the list is short
+ * or not fully used. */
+int spaqr_factorize_forced(spaqr_handle h, double eps, const int32_t* ranks, int32_t nranks);
+
+/* One-shot seminormal solve x = D^-1 W^-1 W^-T D^-1 A^T b (Section 1).
+ * b_dev: M doubles; x_dev: N doubles, original column order. */
+int spaqr_apply(spaqr_handle h, const double* b_dev, double* x_dev);
+
+/* out = W^-1 in or W^-T in, both N doubles in slot space (Section 2.7). */
+int spaqr_apply_op(spaqr_handle h, int32_t op, const double* in_dev, double* out_dev);
+
+/* CGLS on A D^-1 W^-1 (right preconditioning, Section 4) from x0 = 0,
+ * stopping when ||A^T (b - A x)|| <= tol ||A||_2 ||b||.  b_dev: M doubles,
+ * x_dev: N doubles (original order).  info may be NULL.  Returns
+ * SPAQR_NOCONV when max_iter was reached. */
+int spaqr_cgls(spaqr_handle h, const double* b_dev, double tol, int32_t max_iter, double* x_dev,
+               spaqr_cgls_info* info);
+
+/* Statistics of the last factorization (Section 4.2 quantities, the
+ * per-phase ledger, launch and synchronisation counts). */
+int spaqr_factor_stats(spaqr_handle h, spaqr_stats* out);
+
+/* Rank decisions of the last factorization, in decision order (host
+ * buffer of capacity cap); *n receives the count. */
+int spaqr_get_ranks(spaqr_handle h, int32_t* ranks, int32_t cap, int32_t* n);
+
+/* Elementary op i of W (creation order) and its data, copied to host
+ * buffers sized from the descriptor:
+ *   eliminate: mat = [R_ss R_sN] row-major c_s x (c_s + c_N) (upper part of
+ *              R_ss only), slots1 = c_s slots, slots2 = c_N slots;
+ *   scale:     mat = R_pp row-major c_p x c_p, slots1 = c_p slots;
+ *   sparsify:  mat = reflectors row-major c_p x r (unit diagonal, zeros
+ *              above), tau = r scalars, slots1 = c_p slots.
+ * Any output pointer may be NULL. */
+int spaqr_get_op(spaqr_handle h, int32_t i, spaqr_op_desc* desc, double* mat, int32_t* slots1,
+                 int32_t* slots2, double* tau);
+
+/* Release every resource of the handle. */
+int spaqr_destroy(spaqr_handle h);
+
+/* Message of the last error on h (or of the last handle-less failure). */
+const char* spaqr_last_error(spaqr_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPAQR_H */

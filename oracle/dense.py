@@ -60,7 +60,10 @@ def householder_qr(F: np.ndarray, ncols: int | None = None):
     return refl
 
 
-def pivoted_qr(C: np.ndarray, eps: float):
+NOISE = 1000.0
+
+
+def pivoted_qr(C: np.ndarray, eps: float, noise: float = NOISE):
     """Column-pivoted Householder QR of C (m x n), stopped by the rank rule.
 
     Returns (rank, rows, perm, V, tau) where ``rows`` (rank x n) are the first
@@ -69,14 +72,17 @@ def pivoted_qr(C: np.ndarray, eps: float):
     (unit diagonal, zeros above) and ``tau`` their scalars, so that
     Q = H_0 H_1 ... H_{rank-1}.
 
-    Rank rule: rank = number of leading steps i with |R_ii| >= eps |R_00|;
-    rank = 0 when R_00 = 0 (an all-zero or empty matrix).
+    Rank rule: rank = number of leading steps i with |R_ii| >= eps |R_00|
+    and |R_ii| > noise * u * ||C||_F (u the unit roundoff).  The second
+    condition stops at the numerical rank: past it the reflectors would be
+    built from rounding error.  rank = 0 for an all-zero or empty matrix.
     """
     A = np.array(C, dtype=np.float64, copy=True)
     m, n = A.shape
     perm = np.arange(n)
     vn1 = np.sqrt(np.einsum("ij,ij->j", A, A)) if m > 0 else np.zeros(n)
     vn2 = vn1.copy()
+    floor = noise * (EPS / 2) * float(np.sqrt(np.sum(vn1 * vn1)))
     tol3z = math.sqrt(EPS)
     V = np.zeros((m, min(m, n)))
     taus = []
@@ -90,10 +96,10 @@ def pivoted_qr(C: np.ndarray, eps: float):
             vn1[[i, pvt]] = vn1[[pvt, i]]
             vn2[[i, pvt]] = vn2[[pvt, i]]
         v, tau, beta = house(A[i:, i])
+        if abs(beta) <= floor:
+            break
         if i == 0:
             r00 = abs(beta)
-            if r00 == 0.0:
-                break
         elif abs(beta) < eps * r00:
             break
         if tau != 0.0 and i + 1 < n:

@@ -289,8 +289,9 @@ class _State:
             # rows beyond the forced rank must also be dropped from Q^T C
         self.ranks.append(r)
         m, n = C.shape
-        self.ledger["sparsify"][0] += 4 * m * n * r - 2 * r * r * (m + n) + 4 * r ** 3 / 3 + 2 * m * n
-        self.ledger["sparsify"][1] += 8 * (m * n + r * n)
+        phase = "reassign" if kind == "reassign" else "sparsify"
+        self.ledger[phase][0] += 4 * m * n * r - 2 * r * r * (m + n) + 4 * r ** 3 / 3 + 2 * m * n
+        self.ledger[phase][1] += 8 * (m * n + r * n)
         return r, rows, V, tau
 
     # ---- front of an eliminated cluster ----------------------------------
@@ -356,19 +357,17 @@ class _State:
             r0 += g.nrows
         # rows below the diagonal: exact compression, then reassignment (P_s)
         if c_N > 0 and r_s > c_s:
-            E = F[c_s:r_s, c_s:].copy()
-            dense.householder_qr(E)
-            k = min(r_s - c_s, c_N)
-            RE = np.triu(E[:k, :])
-            me = r_s - c_s
-            self.ledger["reassign"][0] += qr_flops(me, c_N)
-            self.ledger["reassign"][1] += 8 * (2 * me * c_N)
+            # the rows below the diagonal are sparsified (rank-revealing QR,
+            # same rule as the interfaces) and the kept rows reassigned
+            E = F[c_s:r_s, c_s:]
+            r, RE, V, tau = self.pivoted(E, "reassign")
             ranges = []
             a = 0
             for c in N_s:
                 ranges.append((a, a + len(c.slots)))
                 a += len(c.slots)
-            self.reassign_rows(RE, nslots, N_s, ranges, s)
+            if r:
+                self.reassign_rows(RE, nslots, N_s, ranges, s)
         s.groups = []
         s.alive = False
         self.live.discard(s)
@@ -555,9 +554,13 @@ def factorize(an: Analysis, eps: float, skip: int, forced_ranks=None) -> Factor:
       column with a cluster already taken in the round; likewise step 2 runs
       in rounds with p ~ q when q is among the columns of p's scaled rows or
       p among q's.  Inside a round the order does not change the result;
-    * rows below the diagonal of an eliminated cluster are first reduced
-      exactly to at most |N_s| rows by a Householder QR, then each goes to
-      the neighbour cluster with the largest sum of its squared entries;
+    * rows below the diagonal of an eliminated cluster are sparsified before
+      they are reassigned (Section 4.2 describes the reassign phase this
+      way): a column-pivoted QR with the rank rule of Section 4 keeps the
+      leading rows of Q^T E, and each kept row goes to the neighbour cluster
+      with the largest sum of its squared entries.  Every rank-revealing QR
+      also stops at the numerical rank (|R_ii| <= 1000 u ||C||_F), where an
+      unpivoted or further-pivoted QR would be steered by rounding error;
     * scaling is applied to all interfaces of the level: every left
       transform U_pp^T first, then every right transform R_pp^-1;
     * step 2 compresses the column block of p over every row except p's

@@ -1,0 +1,180 @@
+// Device kernels that apply the spaQR factor and run CGLS (gfx950, wave64).
+//
+// W is a product of elementary ops (Section 2.7): eliminations
+// [R_ss R_sN; 0 I], scalings R_pp and sparsifications Q_pp = H_1..H_r.
+// W^-1 is applied op by op from the last to the first, W^-T from the first
+// to the last with transposes.  Ops created in one round touch disjoint
+// slots, so a round is one batched launch (one block per op).  Factors may
+// be FP32; every accumulation is FP64, so the preconditioner stays a fixed
+// linear operator for CGLS.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+
+#include "spaqr_impl.h"
+
+namespace spaqr {
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int APPLY_MAX = 6144;  // largest cluster handled by one block (48 KB LDS vector)
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Solve R t = t (upper, column-major, ld) in place in LDS, blocks of 64:
+// wave 0 solves each diagonal block without barriers, all threads update
+// the rows above it.
+template <typename T>
+__device__ void trsv_upper(const T* __restrict__ R, int64_t ld, int n, double* t) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int jb = ((n - 1) / 64) * 64; jb >= 0; jb -= 64) {
+    const int je = min(n, jb + 64);
+    if (tid < 64) {
+      double v = jb + lane < je ? t[jb + lane] : 0.0;
+      for (int j = je - 1; j >= jb; --j) {
+        if (lane == j - jb) v = v / (double)R[j + j * ld];
+        const double tj = __shfl(v, j - jb, 64);
+        if (lane < j - jb) v -= tj * (double)R[jb + lane + j * ld];
+      }
+      if (jb + lane < je) t[jb + lane] = v;
+    }
+    __syncthreads();
+    for (int i = tid; i < jb; i += BS) {
+      double acc = 0.0;
+      for (int j = jb; j < je; ++j) acc += (double)R[i + j * ld] * t[j];
+      t[i] -= acc;
+    }
+    __syncthreads();
+  }
+}
+
+// Solve R^T y = t (R upper) in place, forward over blocks of 64.
+template <typename T>
+__device__ void trsv_upper_t(const T* __restrict__ R, int64_t ld, int n, double* t) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int jb = 0; jb < n; jb += 64) {
+    const int je = min(n, jb + 64);
+    if (tid < 64) {
+      double v = jb + lane < je ? t[jb + lane] : 0.0;
+      for (int j = jb; j < je; ++j) {
+        if (lane == j - jb) v = v / (double)R[j + j * ld];
+        const double yj = __shfl(v, j - jb, 64);
+        if (lane > j - jb && jb + lane < je) v -= (double)R[j + (jb + lane) * ld] * yj;
+      }
+      if (jb + lane < je) t[jb + lane] = v;
+    }
+    __syncthreads();
+    for (int k = je + tid; k < n; k += BS) {
+      const T* col = R + k * ld;
+      double acc = 0.0;
+      for (int j = jb; j < je; ++j) acc += (double)col[j] * t[j];
+      t[k] -= acc;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, int transpose,
+                                              double* __restrict__ x) {
+  const ApplyOp op = ops[blockIdx.x];
+  __shared__ double t[APPLY_MAX];
+  __shared__ double sh[4];
+  const int tid = threadIdx.x;
+  const int n1 = op.n1;
+  const T* R = static_cast<const T*>(op.R);
+  for (int i = tid; i < n1; i += BS) t[i] = x[op.s1[i]];
+  __syncthreads();
+  if (op.kind == 0) {  // eliminate
+    const int cN = op.n2;
+    const T* RN = R + (int64_t)n1 * op.ld;
+    if (!transpose) {
+      for (int i = tid; i < n1; i += BS) {
+        double acc = 0.0;
+        for (int c = 0; c < cN; ++c) acc += (double)RN[i + c * op.ld] * x[op.s2[c]];
+        t[i] -= acc;
+      }
+      __syncthreads();
+      trsv_upper(R, op.ld, n1, t);
+      for (int i = tid; i < n1; i += BS) x[op.s1[i]] = t[i];
+    } else {
+      trsv_upper_t(R, op.ld, n1, t);
+      for (int i = tid; i < n1; i += BS) x[op.s1[i]] = t[i];
+      const int w = tid >> 6, lane = tid & 63;
+      for (int c = w; c < cN; c += 4) {
+        const T* col = RN + c * op.ld;
+        double acc = 0.0;
+        for (int i = lane; i < n1; i += 64) acc += (double)col[i] * t[i];
+        acc = wave_sum(acc);
+        if (lane == 0) atomicAdd(x + op.s2[c], -acc);
+      }
+    }
+  } else if (op.kind == 1) {  // scale
+    if (!transpose)
+      trsv_upper(R, op.ld, n1, t);
+    else
+      trsv_upper_t(R, op.ld, n1, t);
+    for (int i = tid; i < n1; i += BS) x[op.s1[i]] = t[i];
+  } else {  // sparsify: Q = H_0 .. H_{r-1}
+    const int r = op.n2;
+    const T* tau = static_cast<const T*>(op.tau);
+    for (int s = 0; s < r; ++s) {
+      const int k = transpose ? s : r - 1 - s;
+      const T* v = R + (int64_t)k * op.ld;
+      double part = 0.0;
+      for (int i = k + tid; i < n1; i += BS) part += (double)v[i] * t[i];
+      const double dot = block_sum(part, sh);
+      const double f = (double)tau[k] * dot;
+      for (int i = k + tid; i < n1; i += BS) t[i] -= f * (double)v[i];
+      __syncthreads();
+    }
+    for (int i = tid; i < n1; i += BS) x[op.s1[i]] = t[i];
+  }
+}
+
+__global__ void k_spmv(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                       const double* __restrict__ val, const double* __restrict__ x,
+                       double* __restrict__ y, int64_t rows) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  double acc = 0.0;
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) acc += val[e] * x[idx[e]];
+  y[r] = acc;
+}
+
+}  // namespace
+
+template <typename T>
+void launch_apply_batch(const ApplyOp* d_ops, int n, int max_n1, bool transpose, double* x,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  if (max_n1 > APPLY_MAX) throw Error(SPAQR_EARG, "cluster too large for the apply kernel");
+  hipLaunchKernelGGL(k_apply<T>, dim3(n), dim3(BS), 0, s, d_ops, transpose ? 1 : 0, x);
+  SPAQR_HIP(hipGetLastError());
+}
+
+void launch_spmv(const int64_t* ptr, const int32_t* idx, const double* val, const double* x,
+                 double* y, int64_t rows, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_spmv, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, ptr, idx, val, x, y,
+                     rows);
+  SPAQR_HIP(hipGetLastError());
+}
+
+template void launch_apply_batch<double>(const ApplyOp*, int, int, bool, double*, hipStream_t);
+template void launch_apply_batch<float>(const ApplyOp*, int, int, bool, double*, hipStream_t);
+
+}  // namespace spaqr

@@ -1,0 +1,227 @@
+// extern "C" boundary of libspaqr: argument checks, error capture, and
+// dispatch into the host analysis, the device factorization and the
+// solvers.  No C++ exception leaves this file.
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "handle.h"
+
+struct spaqr_handle_s {
+  spaqr::Handle h;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+template <class F>
+int guard(spaqr_handle h, F&& f) {
+  try {
+    return f();
+  } catch (const spaqr::Error& e) {
+    (h ? h->h.err : g_err) = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    (h ? h->h.err : g_err) = "host allocation failed";
+    return SPAQR_ENOMEM;
+  } catch (const std::exception& e) {
+    (h ? h->h.err : g_err) = e.what();
+    return SPAQR_EARG;
+  } catch (...) {
+    (h ? h->h.err : g_err) = "unknown error";
+    return SPAQR_EARG;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int spaqr_analyze(const int64_t* row_ptr, const int32_t* col_idx, const double* vals, int64_t M,
+                  int64_t N, const spaqr_options* opt, spaqr_handle* out) {
+  return guard(nullptr, [&]() -> int {
+    if (!out || !opt) throw spaqr::Error(SPAQR_EARG, "null argument");
+    *out = nullptr;
+    if (opt->precision != SPAQR_FP64 && opt->precision != SPAQR_FP32_FACTOR)
+      throw spaqr::Error(SPAQR_EARG, "unknown precision");
+    std::unique_ptr<spaqr_handle_s> h(new spaqr_handle_s());
+    h->h.opt = *opt;
+    spaqr::analyze_plan(h->h.P, row_ptr, col_idx, vals, M, N, *opt);
+    *out = h.release();
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_get_ordering(spaqr_handle h, int32_t* col_perm, int32_t* row_owner) {
+  return guard(h, [&]() -> int {
+    if (!h) throw spaqr::Error(SPAQR_EARG, "null handle");
+    const spaqr::Plan& P = h->h.P;
+    if (col_perm) {
+      int64_t k = 0;
+      for (int f : P.finest)
+        for (int j : P.clusters[f].cells) col_perm[k++] = j;
+    }
+    if (row_owner)
+      for (int64_t r = 0; r < P.M; ++r) row_owner[r] = P.clusters[P.row_owner[r]].finest_index;
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_set_values(spaqr_handle h, const double* vals_dev) {
+  return guard(h, [&]() -> int {
+    if (!h || !vals_dev) throw spaqr::Error(SPAQR_EARG, "null argument");
+    spaqr::Handle& H = h->h;
+    H.ensure_device();
+    std::vector<double> v(H.P.nnz);
+    SPAQR_HIP(hipMemcpyAsync(v.data(), vals_dev, v.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             H.stream));
+    SPAQR_HIP(hipStreamSynchronize(H.stream));
+    spaqr::rescale_values(H.P, v.data());
+    std::vector<double> at(H.P.nnz);
+    for (int64_t e = 0; e < H.P.nnz; ++e) at[e] = H.P.ahat[H.P.at_src[e]];
+    SPAQR_HIP(hipMemcpy(H.d_ahat, H.P.ahat.data(), H.P.nnz * sizeof(double), hipMemcpyHostToDevice));
+    SPAQR_HIP(hipMemcpy(H.d_ahatT, at.data(), H.P.nnz * sizeof(double), hipMemcpyHostToDevice));
+    SPAQR_HIP(hipMemcpy(H.d_D, H.P.D.data(), H.P.N * sizeof(double), hipMemcpyHostToDevice));
+    H.factored = false;
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_factorize(spaqr_handle h, double eps) {
+  return guard(h, [&]() -> int {
+    if (!h) throw spaqr::Error(SPAQR_EARG, "null handle");
+    spaqr::factorize(h->h, eps, nullptr, 0);
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_factorize_forced(spaqr_handle h, double eps, const int32_t* ranks, int32_t nranks) {
+  return guard(h, [&]() -> int {
+    if (!h || (!ranks && nranks > 0) || nranks < 0) throw spaqr::Error(SPAQR_EARG, "bad argument");
+    static const int32_t none = 0;
+    spaqr::factorize(h->h, eps, ranks ? ranks : &none, nranks);
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_apply(spaqr_handle h, const double* b_dev, double* x_dev) {
+  return guard(h, [&]() -> int {
+    if (!h || !b_dev || !x_dev) throw spaqr::Error(SPAQR_EARG, "null argument");
+    spaqr::csne(h->h, b_dev, x_dev);
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_apply_op(spaqr_handle h, int32_t op, const double* in_dev, double* out_dev) {
+  return guard(h, [&]() -> int {
+    if (!h || !in_dev || !out_dev) throw spaqr::Error(SPAQR_EARG, "null argument");
+    if (op != SPAQR_WINV && op != SPAQR_WINVT) throw spaqr::Error(SPAQR_EARG, "unknown op");
+    spaqr::Handle& H = h->h;
+    if (!H.factored) throw spaqr::Error(SPAQR_ESTATE, "factorize first");
+    if (in_dev != out_dev)
+      SPAQR_HIP(hipMemcpyAsync(out_dev, in_dev, H.P.N * sizeof(double), hipMemcpyDeviceToDevice, H.stream));
+    spaqr::apply_op(H, op == SPAQR_WINVT, out_dev);
+    SPAQR_HIP(hipStreamSynchronize(H.stream));
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_cgls(spaqr_handle h, const double* b_dev, double tol, int32_t max_iter, double* x_dev,
+               spaqr_cgls_info* info) {
+  return guard(h, [&]() -> int {
+    if (!h || !b_dev || !x_dev) throw spaqr::Error(SPAQR_EARG, "null argument");
+    return spaqr::cgls(h->h, b_dev, tol, max_iter, x_dev, info);
+  });
+}
+
+int spaqr_factor_stats(spaqr_handle h, spaqr_stats* out) {
+  return guard(h, [&]() -> int {
+    if (!h || !out) throw spaqr::Error(SPAQR_EARG, "null argument");
+    if (!h->h.factored) throw spaqr::Error(SPAQR_ESTATE, "factorize first");
+    *out = h->h.stats;
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_get_ranks(spaqr_handle h, int32_t* ranks, int32_t cap, int32_t* n) {
+  return guard(h, [&]() -> int {
+    if (!h || !n) throw spaqr::Error(SPAQR_EARG, "null argument");
+    if (!h->h.factored) throw spaqr::Error(SPAQR_ESTATE, "factorize first");
+    const auto& r = h->h.ranks;
+    *n = (int32_t)r.size();
+    if (ranks)
+      for (int32_t i = 0; i < cap && i < (int32_t)r.size(); ++i) ranks[i] = r[i];
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_get_op(spaqr_handle h, int32_t i, spaqr_op_desc* desc, double* mat, int32_t* slots1,
+                 int32_t* slots2, double* tau) {
+  return guard(h, [&]() -> int {
+    if (!h) throw spaqr::Error(SPAQR_EARG, "null handle");
+    spaqr::Handle& H = h->h;
+    if (!H.factored) throw spaqr::Error(SPAQR_ESTATE, "factorize first");
+    if (i < 0 || i >= (int32_t)H.ops.size()) throw spaqr::Error(SPAQR_EARG, "op index out of range");
+    const spaqr::OpRec& o = H.ops[i];
+    if (desc) {
+      desc->kind = o.kind;
+      desc->n1 = o.n1;
+      desc->n2 = o.kind == 1 ? 0 : o.n2;
+      desc->round = o.round;
+      desc->level = o.level;
+    }
+    if (slots1)
+      for (size_t k = 0; k < o.s1.size(); ++k) slots1[k] = o.s1[k];
+    if (slots2)
+      for (size_t k = 0; k < o.s2.size(); ++k) slots2[k] = o.s2[k];
+    const size_t es = H.precision == SPAQR_FP32_FACTOR ? 4 : 8;
+    auto fetch = [&](const void* src, int64_t ld, int rows, int cols, std::vector<double>& out) {
+      std::vector<char> raw((size_t)ld * cols * es);
+      if (!raw.empty())
+        SPAQR_HIP(hipMemcpy(raw.data(), src, raw.size(), hipMemcpyDeviceToHost));
+      out.assign((size_t)rows * cols, 0.0);
+      for (int c = 0; c < cols; ++c)
+        for (int r = 0; r < rows; ++r) {
+          const size_t k = (size_t)r + (size_t)c * ld;
+          out[(size_t)r * cols + c] =
+              es == 4 ? (double)reinterpret_cast<const float*>(raw.data())[k] : reinterpret_cast<const double*>(raw.data())[k];
+        }
+    };
+    if (mat || tau) {
+      SPAQR_HIP(hipStreamSynchronize(H.stream));
+      std::vector<double> m;
+      if (o.kind == 0) {
+        fetch(o.R, o.ld, o.n1, o.n1 + o.n2, m);
+        for (int r = 0; r < o.n1; ++r)
+          for (int c = 0; c < r; ++c) m[(size_t)r * (o.n1 + o.n2) + c] = 0.0;
+      } else if (o.kind == 1) {
+        fetch(o.R, o.ld, o.n1, o.n1, m);
+        for (int r = 0; r < o.n1; ++r)
+          for (int c = 0; c < r; ++c) m[(size_t)r * o.n1 + c] = 0.0;
+      } else {
+        fetch(o.R, o.ld, o.n1, o.n2, m);
+      }
+      if (mat) std::memcpy(mat, m.data(), m.size() * sizeof(double));
+      if (tau && o.kind == 2 && o.n2 > 0) {
+        std::vector<double> t;
+        fetch(o.tau, 1, 1, o.n2, t);
+        std::memcpy(tau, t.data(), t.size() * sizeof(double));
+      }
+    }
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_destroy(spaqr_handle h) {
+  if (!h) return SPAQR_OK;
+  return guard(nullptr, [&]() -> int {
+    delete h;
+    return SPAQR_OK;
+  });
+}
+
+const char* spaqr_last_error(spaqr_handle h) { return h ? h->h.err.c_str() : g_err.c_str(); }
+
+}  // extern "C"

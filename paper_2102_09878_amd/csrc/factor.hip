@@ -1,0 +1,1277 @@
+// Level-by-level spaQR factorization on one GPU (Algorithm 1 of
+// Gnanasekaran & Darve, Sections 2.3-2.7).
+//
+// Device data, host metadata: every row group (a dense block of rows owned
+// by one cluster, stored over an explicit list of column slots) lives in
+// device memory; the host keeps the block structure (which clusters each
+// group touches, live column slots of each cluster) and turns each phase
+// into a few batched launches over descriptor arrays: gather fronts -> QR
+// -> write back.  The host reads back only what decides structure: owners
+// of reassigned rows and the ranks chosen by the rank-revealing QRs.
+//
+// Scheduling readings (the paper leaves the order open):
+//  * the clusters of one level are eliminated in rounds; a round takes, in
+//    id order, every pending cluster sharing no front row and no front
+//    column with one already taken; one round = one batched launch chain;
+//  * step 2 runs in rounds the same way, p ~ q when q is a column cluster
+//    of p's scaled rows or p one of q's;
+//  * scaling applies every left transform U_pp^T, then every right R_pp^-1.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+
+#include "handle.h"
+
+namespace spaqr {
+
+// ---------------------------------------------------------------------------
+// memory
+// ---------------------------------------------------------------------------
+static constexpr size_t kChunk = size_t(256) << 20;
+
+Arena::~Arena() { release(); }
+void* Arena::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  while (cur_ < chunks_.size() && chunks_[cur_].off + bytes > chunks_[cur_].size) ++cur_;
+  if (cur_ == chunks_.size()) {
+    Chunk c{nullptr, std::max(kChunk, bytes), 0};
+    if (hipMalloc(&c.ptr, c.size) != hipSuccess) throw Error(SPAQR_ENOMEM, "device allocation failed");
+    chunks_.push_back(c);
+  }
+  Chunk& c = chunks_[cur_];
+  void* p = c.ptr + c.off;
+  c.off += bytes;
+  used_total_ += bytes;
+  return p;
+}
+void Arena::reset() {
+  for (auto& c : chunks_) c.off = 0;
+  cur_ = 0;
+  used_total_ = 0;
+}
+void Arena::release() {
+  for (auto& c : chunks_) (void)hipFree(c.ptr);
+  chunks_.clear();
+  cur_ = 0;
+  used_total_ = 0;
+}
+size_t Arena::capacity() const {
+  size_t s = 0;
+  for (auto& c : chunks_) s += c.size;
+  return s;
+}
+
+Staging::~Staging() { release(); }
+void* Staging::alloc(size_t bytes) {
+  bytes = (bytes + 63) & ~size_t(63);
+  if (bytes == 0) bytes = 64;
+  while (cur_ < chunks_.size() && chunks_[cur_].off + bytes > chunks_[cur_].size) ++cur_;
+  if (cur_ == chunks_.size()) {
+    Chunk c{nullptr, std::max(size_t(64) << 20, bytes), 0};
+    if (hipHostMalloc((void**)&c.ptr, c.size, hipHostMallocDefault) != hipSuccess)
+      throw Error(SPAQR_ENOMEM, "pinned host allocation failed");
+    chunks_.push_back(c);
+  }
+  Chunk& c = chunks_[cur_];
+  void* p = c.ptr + c.off;
+  c.off += bytes;
+  return p;
+}
+void Staging::reset() {
+  for (auto& c : chunks_) c.off = 0;
+  cur_ = 0;
+}
+void Staging::release() {
+  for (auto& c : chunks_) (void)hipHostFree(c.ptr);
+  chunks_.clear();
+  cur_ = 0;
+}
+
+Handle::~Handle() {
+  try {
+    release_device();
+  } catch (...) {
+  }
+}
+
+void Handle::release_device() {
+  if (!dev_ready) return;
+  (void)hipStreamSynchronize(stream);
+  for (void* p : {(void*)d_ahat, (void*)d_rp, (void*)d_ci, (void*)d_ahatT, (void*)d_atp, (void*)d_ati,
+                  (void*)d_init_dst, (void*)d_D, (void*)d_cg})
+    if (p) (void)hipFree(p);
+  if (h_sc) (void)hipHostFree(h_sc);
+  d_ahat = d_ahatT = d_D = d_cg = nullptr;
+  d_rp = d_atp = nullptr;
+  d_ci = d_ati = nullptr;
+  d_init_dst = nullptr;
+  h_sc = nullptr;
+  arena.release();
+  stage.release();
+  dev_ready = false;
+}
+
+template <class V>
+static V* dcopy(const std::vector<V>& h, size_t& bytes) {
+  V* d = nullptr;
+  const size_t b = std::max<size_t>(1, h.size()) * sizeof(V);
+  if (hipMalloc(&d, b) != hipSuccess) throw Error(SPAQR_ENOMEM, "device allocation failed");
+  if (!h.empty()) SPAQR_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
+  bytes += b;
+  return d;
+}
+
+void Handle::ensure_device() {
+  if (dev_ready) return;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) throw Error(SPAQR_EHIP, "no HIP device");
+  SPAQR_HIP(hipSetDevice(opt.device));
+  stream = static_cast<hipStream_t>(opt.stream);
+  plan_bytes = 0;
+  d_rp = dcopy(P.row_ptr, plan_bytes);
+  d_ci = dcopy(P.col_idx, plan_bytes);
+  d_ahat = dcopy(P.ahat, plan_bytes);
+  std::vector<double> at(P.nnz);
+  for (int64_t e = 0; e < P.nnz; ++e) at[e] = P.ahat[P.at_src[e]];
+  d_ahatT = dcopy(at, plan_bytes);
+  d_atp = dcopy(P.at_ptr, plan_bytes);
+  d_ati = dcopy(P.at_idx, plan_bytes);
+  d_init_dst = dcopy(P.init_dst, plan_bytes);
+  d_D = dcopy(P.D, plan_bytes);
+  SPAQR_HIP(hipHostMalloc((void**)&h_sc, 64 * sizeof(double), hipHostMallocDefault));
+  dev_ready = true;
+}
+
+// ---------------------------------------------------------------------------
+// factorization
+// ---------------------------------------------------------------------------
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+double qr_flops(double m, double n) {
+  return m >= n ? 2.0 * m * n * n - 2.0 * n * n * n / 3.0 : 2.0 * n * m * m - 2.0 * m * m * m / 3.0;
+}
+
+enum Phase { PH_ELIM = 0, PH_REASSIGN = 1, PH_SCALE = 2, PH_SPARSIFY = 3, PH_MERGE = 4 };
+
+// Every rank-revealing QR stops at the numerical rank: a pivot with
+// |R_ii| <= kNoiseRank * u * ||C||_F is rounding error, and reflectors built
+// from it (and rows or columns kept because of it) would differ from run to
+// run and from any other implementation.
+constexpr double kNoiseRank = 1000.0;
+template <typename T>
+constexpr double unit_roundoff() {
+  return sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
+}
+
+template <typename T>
+class Factorizer {
+ public:
+  Factorizer(Handle& h, double eps, const int* forced, int nforced)
+      : H(h), P(h.P), st(h.stream), eps_(eps), forced_(forced), nforced_(nforced) {}
+
+  void run();
+
+ private:
+  struct RG {
+    int owner = -1;
+    T* data = nullptr;
+    int64_t ld = 0;
+    int nrows = 0;
+    std::vector<int> slots;
+    std::vector<int> clus;  // sorted
+    int role = 0;           // 1: scaled rows p1, 2: rows below them p2
+    bool alive = true;
+  };
+  struct RC {
+    std::vector<int> slots;
+    std::vector<int> groups;
+    bool alive = false;
+  };
+
+  Handle& H;
+  Plan& P;
+  hipStream_t st;
+  double eps_;
+  const int* forced_;
+  int nforced_;
+  int fpos_ = 0;
+  std::vector<RG> G;
+  std::vector<RC> C;
+  std::set<int> live;
+  std::vector<int> pos;
+  int level_ = 0, round_ = 0;
+  double* tbuf_ = nullptr;
+  size_t tbuf_cap_ = 0;
+  int launches_ = 0, syncs_ = 0;
+  double flops_[5] = {0, 0, 0, 0, 0}, bytes_[5] = {0, 0, 0, 0, 0};
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> timers_;
+
+  // ---- helpers ----
+  T* talloc(int64_t elems) { return static_cast<T*>(H.arena.alloc(std::max<int64_t>(1, elems) * sizeof(T))); }
+  static int64_t pad(int64_t m) { return std::max<int64_t>(8, (m + 7) / 8 * 8); }
+  static bool has(const std::vector<int>& v, int c) { return std::binary_search(v.begin(), v.end(), c); }
+
+  template <class D>
+  D* upload(const std::vector<D>& v) {
+    if (v.empty()) return nullptr;
+    const size_t b = v.size() * sizeof(D);
+    void* hp = H.stage.alloc(b);
+    std::memcpy(hp, v.data(), b);
+    void* dp = H.arena.alloc(b);
+    SPAQR_HIP(hipMemcpyAsync(dp, hp, b, hipMemcpyHostToDevice, st));
+    return static_cast<D*>(dp);
+  }
+
+  // int pool: colmaps etc. collected per launch, uploaded once
+  struct IntPool {
+    std::vector<int> v;
+    size_t add(const std::vector<int>& a) {
+      size_t o = v.size();
+      v.insert(v.end(), a.begin(), a.end());
+      return o;
+    }
+  };
+
+  std::vector<int> colmap(const RG& g, const std::vector<int>& cols, bool required) {
+    for (size_t i = 0; i < g.slots.size(); ++i) pos[g.slots[i]] = (int)i;
+    std::vector<int> m(cols.size());
+    bool ok = true;
+    for (size_t c = 0; c < cols.size(); ++c) {
+      m[c] = pos[cols[c]];
+      ok = ok && m[c] >= 0;
+    }
+    for (int s : g.slots) pos[s] = -1;
+    if (required && !ok) throw Error(SPAQR_EARG, "internal: group lacks a column of a touched cluster");
+    return m;
+  }
+
+  std::vector<int> slots_of(const std::vector<int>& clus) {
+    std::vector<int> s;
+    for (int c : clus) s.insert(s.end(), C[c].slots.begin(), C[c].slots.end());
+    return s;
+  }
+
+  void sync() {
+    SPAQR_HIP(hipStreamSynchronize(st));
+    ++syncs_;
+  }
+
+  int next_forced() {
+    if (!forced_) return -1;
+    if (fpos_ >= nforced_) throw Error(SPAQR_EARG, "forced rank list is too short");
+    return forced_[fpos_++];
+  }
+
+  void timer_begin(int phase) {
+    hipEvent_t a, b;
+    SPAQR_HIP(hipEventCreate(&a));
+    SPAQR_HIP(hipEventCreate(&b));
+    SPAQR_HIP(hipEventRecord(a, st));
+    timers_.push_back({phase, {a, b}});
+  }
+  void timer_end() { SPAQR_HIP(hipEventRecord(timers_.back().second.second, st)); }
+
+  void kill_group(int g) { G[g].alive = false; }
+
+  std::vector<int> live_groups() {
+    std::vector<int> out;
+    for (int c : live)
+      for (int g : C[c].groups) out.push_back(g);
+    return out;
+  }
+
+  void record_op(int kind, int phase, const void* R, const void* tau, int64_t ld, int n1, int n2,
+                 const std::vector<int>& s1, const std::vector<int>& s2) {
+    OpRec o;
+    o.kind = kind;
+    o.level = level_;
+    o.round = round_;
+    o.phase = phase;
+    o.R = R;
+    o.tau = tau;
+    o.ld = ld;
+    o.n1 = n1;
+    o.n2 = n2;
+    o.s1 = s1;
+    o.s2 = s2;
+    H.ops.push_back(std::move(o));
+  }
+
+  // Debug hook: with SPAQR_DEBUG_DIR set, every gathered front is written to
+  // <dir>/<tag>_L<level>_<key0>_<key1>.bin as int64 m, n; int32 slots[n];
+  // double data[m*n] column-major.  Off (and free) otherwise.
+  void dump_front(const char* tag, int cluster, const T* F, int64_t ld, int m, int n,
+                  const std::vector<int>& cols) {
+    static const char* dir = std::getenv("SPAQR_DEBUG_DIR");
+    if (!dir) return;
+    sync();
+    std::vector<T> buf((size_t)ld * std::max(1, n));
+    SPAQR_HIP(hipMemcpy(buf.data(), F, buf.size() * sizeof(T), hipMemcpyDeviceToHost));
+    const Cluster& c = P.clusters[cluster];
+    std::string path = std::string(dir) + "/" + tag + "_L" + std::to_string(level_) + "_" +
+                       std::to_string(c.key0) + "_" + std::to_string(c.key1) + ".bin";
+    FILE* fp = std::fopen(path.c_str(), "wb");
+    if (!fp) return;
+    int64_t mn[2] = {m, n};
+    std::fwrite(mn, sizeof(int64_t), 2, fp);
+    std::vector<int32_t> s(cols.begin(), cols.end());
+    std::fwrite(s.data(), sizeof(int32_t), s.size(), fp);
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < m; ++i) {
+        const double v = (double)buf[(size_t)i + (size_t)j * ld];
+        std::fwrite(&v, sizeof(double), 1, fp);
+      }
+    std::fclose(fp);
+  }
+
+  void ensure_tbuf(size_t n) {
+    if (n > tbuf_cap_) {
+      tbuf_cap_ = std::max<size_t>(n, 2 * tbuf_cap_);
+      tbuf_ = static_cast<double*>(H.arena.alloc(tbuf_cap_ * 32 * 32 * sizeof(double)));
+    }
+  }
+
+  void run_qr(const std::vector<QRDesc>& q) {
+    if (q.empty()) return;
+    ensure_tbuf(q.size());
+    QRDesc* d = upload(q);
+    launch_qr<T>(d, q, tbuf_, st, &launches_);
+  }
+
+  int* flags_ = nullptr;
+  int nflags_ = 0;
+
+  void init_groups();
+  void eliminate_level(int m);
+  void eliminate_round(const std::vector<int>& sel);
+  void scale_all();
+  void step1_all();
+  void step2_round(const std::vector<int>& sel);
+  void vanish(int p);
+  void merge(int m);
+  void reassign_group_rows(int g);
+  void build_apply();
+};
+
+template <typename T>
+void Factorizer<T>::init_groups() {
+  const size_t nc = P.clusters.size();
+  C.assign(nc, RC());
+  pos.assign(P.N, -1);
+  T* base = talloc(P.init_elems);
+  SPAQR_HIP(hipMemsetAsync(base, 0, std::max<int64_t>(1, P.init_elems) * sizeof(T), st));
+  launch_scatter_csr<T>(base, H.d_init_dst, H.d_ahat, P.nnz, st);
+  launches_ += 2;
+  for (const InitGroup& ig : P.init_groups) {
+    RG g;
+    g.owner = ig.owner;
+    g.data = base + ig.offset;
+    g.ld = ig.ld;
+    g.nrows = (int)ig.rows.size();
+    for (int c : ig.clus) g.slots.insert(g.slots.end(), P.clusters[c].cells.begin(), P.clusters[c].cells.end());
+    g.clus = ig.clus;
+    C[ig.owner].groups.push_back((int)G.size());
+    G.push_back(std::move(g));
+  }
+  for (int f : P.finest) {
+    C[f].slots = P.clusters[f].cells;
+    C[f].alive = true;
+    live.insert(f);
+  }
+}
+
+// ---- elimination (Section 2.3) ----------------------------------------------
+template <typename T>
+void Factorizer<T>::eliminate_level(int m) {
+  std::vector<int> pending;
+  for (int c : live)
+    if (P.nodes[P.clusters[c].sep].level == m) pending.push_back(c);
+  round_ = 0;
+  if (m == 1 && !pending.empty()) {
+    int s = pending[0];
+    int rows = 0;
+    for (int g : C[s].groups) rows += G[g].nrows;
+    H.stats.top_cols = (int)C[s].slots.size();
+    H.stats.top_rows = rows;
+  }
+  while (!pending.empty()) {
+    // neighbours of every pending cluster from the current structure
+    std::vector<std::vector<int>> nb(pending.size());
+    for (size_t i = 0; i < pending.size(); ++i) {
+      const int s = pending[i];
+      std::vector<int> u;
+      for (int g : C[s].groups) u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
+      for (int c : live) {
+        if (c == s) continue;
+        for (int g : C[c].groups)
+          if (has(G[g].clus, s)) u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
+      }
+      std::sort(u.begin(), u.end());
+      u.erase(std::unique(u.begin(), u.end()), u.end());
+      u.erase(std::remove(u.begin(), u.end(), s), u.end());
+      nb[i] = std::move(u);
+    }
+    std::vector<int> sel, rest;
+    std::vector<size_t> seli;
+    for (size_t i = 0; i < pending.size(); ++i) {
+      bool ok = true;
+      for (size_t j : seli)
+        if (has(nb[i], pending[j]) || has(nb[j], pending[i])) ok = false;
+      if (ok) {
+        sel.push_back(pending[i]);
+        seli.push_back(i);
+      } else {
+        rest.push_back(pending[i]);
+      }
+    }
+    eliminate_round(sel);
+    pending.swap(rest);
+    ++round_;
+  }
+}
+
+template <typename T>
+void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
+  struct Front {
+    int s;
+    std::vector<int> owned, foreign, nb, cols;
+    int m, n, cs, cN, rs;
+    T* F;
+    int64_t ld;
+  };
+  std::vector<Front> fr(sel.size());
+  IntPool pool;
+  std::vector<GatherDesc> gd;
+  std::vector<size_t> gd_map;
+  std::vector<QRDesc> qd;
+  int maxc = 0;
+  timer_begin(PH_ELIM);
+  for (size_t i = 0; i < sel.size(); ++i) {
+    Front& f = fr[i];
+    f.s = sel[i];
+    f.owned = C[f.s].groups;
+    std::vector<int> u;
+    for (int g : f.owned) u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
+    for (int c : live) {
+      if (c == f.s) continue;
+      for (int g : C[c].groups)
+        if (has(G[g].clus, f.s)) {
+          f.foreign.push_back(g);
+          u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
+        }
+    }
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    u.erase(std::remove(u.begin(), u.end(), f.s), u.end());
+    f.nb = u;
+    f.cols = C[f.s].slots;
+    std::vector<int> ns = slots_of(f.nb);
+    f.cols.insert(f.cols.end(), ns.begin(), ns.end());
+    f.cs = (int)C[f.s].slots.size();
+    f.n = (int)f.cols.size();
+    f.cN = f.n - f.cs;
+    f.rs = 0;
+    for (int g : f.owned) f.rs += G[g].nrows;
+    f.m = f.rs;
+    for (int g : f.foreign) f.m += G[g].nrows;
+    if (f.rs < f.cs) throw Error(SPAQR_EARG, "internal: cluster with fewer rows than columns");
+    f.ld = pad(f.m);
+    f.F = talloc(f.ld * f.n);
+    int64_t row0 = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int g : pass == 0 ? f.owned : f.foreign) {
+        GatherDesc d{};
+        d.src = G[g].data;
+        d.dst = f.F;
+        d.src_ld = G[g].ld;
+        d.dst_ld = f.ld;
+        d.row0 = row0;
+        d.col0 = 0;
+        d.nrows = G[g].nrows;
+        d.ncols = f.n;
+        d.transpose = 0;
+        gd_map.push_back(pool.add(colmap(G[g], f.cols, false)));
+        gd.push_back(d);
+        row0 += G[g].nrows;
+      }
+    maxc = std::max(maxc, f.n);
+    QRDesc q{};
+    q.A = f.F;
+    q.tau = talloc(std::max(1, std::min(f.m, f.cs)));
+    q.lda = f.ld;
+    q.m = f.m;
+    q.n = f.n;
+    q.k = f.cs;
+    qd.push_back(q);
+    flops_[PH_ELIM] += qr_flops(f.m, f.cs) + 4.0 * f.m * f.cs * f.cN - 2.0 * f.cs * f.cs * f.cN;
+    bytes_[PH_ELIM] += 2.0 * sizeof(T) * f.m * f.n;
+  }
+  int* dpool = upload(pool.v);
+  for (size_t i = 0; i < gd.size(); ++i) gd[i].colmap = dpool + gd_map[i];
+  launch_gather<T>(upload(gd), (int)gd.size(), maxc, st);
+  ++launches_;
+  for (auto& f : fr) dump_front("elim", f.s, f.F, f.ld, f.m, f.n, f.cols);
+  run_qr(qd);
+  timer_end();
+
+  // factor ops, rows of other owners, rows below the diagonal
+  std::vector<PQRDesc> qe;
+  std::vector<size_t> ext;
+  for (size_t i = 0; i < fr.size(); ++i) {
+    Front& f = fr[i];
+    std::vector<int> s2(f.cols.begin() + f.cs, f.cols.end());
+    record_op(0, PH_ELIM, f.F, nullptr, f.ld, f.cs, f.cN, C[f.s].slots, s2);
+    int64_t off = f.rs;
+    for (int g : f.foreign) {
+      RG& gr = G[g];
+      gr.data = f.F + off + (int64_t)f.cs * f.ld;
+      gr.ld = f.ld;
+      gr.slots = s2;
+      gr.clus = f.nb;
+      gr.role = 0;
+      off += gr.nrows;
+    }
+    if (f.cN > 0 && f.rs > f.cs) {
+      // rows below the diagonal: sparsified by a rank-revealing QR in place
+      PQRDesc q{};
+      q.A = f.F + f.cs + (int64_t)f.cs * f.ld;
+      q.lda = f.ld;
+      q.m = f.rs - f.cs;
+      q.n = f.cN;
+      q.noise = kNoiseRank * unit_roundoff<T>();
+      q.work = static_cast<double*>(H.arena.alloc(3 * std::max(1, q.n) * sizeof(double)));
+      q.forced = next_forced();
+      qe.push_back(q);
+      ext.push_back(i);
+    }
+    for (int g : f.owned) kill_group(g);
+    C[f.s].groups.clear();
+    C[f.s].alive = false;
+    live.erase(f.s);
+  }
+  if (qe.empty()) return;
+  timer_begin(PH_REASSIGN);
+  int* d_rank = static_cast<int*>(H.arena.alloc(qe.size() * sizeof(int)));
+  for (size_t e = 0; e < qe.size(); ++e) qe[e].rank_out = d_rank + e;
+  launch_pqr<T>(upload(qe), (int)qe.size(), eps_, st);
+  ++launches_;
+  // owner of each kept row (Section 2.3: maximum-norm heuristic)
+  IntPool op;
+  std::vector<OwnerDesc> od;
+  std::vector<size_t> od_cm, od_off;
+  int* d_owner_all = nullptr;
+  std::vector<size_t> owner_base;
+  size_t nown = 0;
+  for (size_t e = 0; e < ext.size(); ++e) {
+    Front& f = fr[ext[e]];
+    const int k = std::min(f.rs - f.cs, f.cN);
+    owner_base.push_back(nown);
+    nown += k;
+  }
+  d_owner_all = static_cast<int*>(H.arena.alloc(std::max<size_t>(1, nown) * sizeof(int)));
+  for (size_t e = 0; e < ext.size(); ++e) {
+    Front& f = fr[ext[e]];
+    OwnerDesc d{};
+    d.A = qe[e].A;
+    d.lda = f.ld;
+    d.nrows = std::min(f.rs - f.cs, f.cN);
+    d.nrows_dev = d_rank + e;
+    d.ncl = (int)f.nb.size();
+    std::vector<int> cm(f.cN);
+    std::iota(cm.begin(), cm.end(), 0);
+    std::vector<int> off(f.nb.size() + 1, 0);
+    for (size_t q = 0; q < f.nb.size(); ++q) off[q + 1] = off[q] + (int)C[f.nb[q]].slots.size();
+    od_cm.push_back(op.add(cm));
+    od_off.push_back(op.add(off));
+    d.owner = d_owner_all + owner_base[e];
+    od.push_back(d);
+  }
+  int* dop = upload(op.v);
+  for (size_t e = 0; e < od.size(); ++e) {
+    od[e].colmap = dop + od_cm[e];
+    od[e].cl_off = dop + od_off[e];
+  }
+  launch_owner<T>(upload(od), (int)od.size(), st);
+  ++launches_;
+  int* h_owner = static_cast<int*>(H.stage.alloc((std::max<size_t>(1, nown) + qe.size()) * sizeof(int)));
+  int* h_rank = h_owner + std::max<size_t>(1, nown);
+  SPAQR_HIP(hipMemcpyAsync(h_owner, d_owner_all, std::max<size_t>(1, nown) * sizeof(int),
+                           hipMemcpyDeviceToHost, st));
+  SPAQR_HIP(hipMemcpyAsync(h_rank, d_rank, qe.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+  sync();
+  // new groups, one per (front, owner), appended in front order
+  IntPool rp;
+  std::vector<RowCopyDesc> rd;
+  std::vector<size_t> rd_rows;
+  int maxcols = 0;
+  for (size_t e = 0; e < ext.size(); ++e) {
+    Front& f = fr[ext[e]];
+    const int k = h_rank[e];
+    H.ranks.push_back(k);
+    const double m = qe[e].m, n = qe[e].n;
+    flops_[PH_REASSIGN] += 4 * m * n * k - 2.0 * k * k * (m + n) + 4.0 * k * k * k / 3 + 2 * m * n;
+    bytes_[PH_REASSIGN] += sizeof(T) * (2 * m * n);
+    std::vector<std::vector<int>> by(f.nb.size());
+    for (int r = 0; r < k; ++r) by[h_owner[owner_base[e] + r]].push_back(r);
+    std::vector<int> s2(f.cols.begin() + f.cs, f.cols.end());
+    for (size_t q = 0; q < f.nb.size(); ++q) {
+      if (by[q].empty()) continue;
+      RG g;
+      g.owner = f.nb[q];
+      g.nrows = (int)by[q].size();
+      g.ld = pad(g.nrows);
+      g.data = talloc(g.ld * f.cN);
+      g.slots = s2;
+      g.clus = f.nb;
+      RowCopyDesc d{};
+      d.src = qe[e].A;
+      d.dst = g.data;
+      d.src_ld = f.ld;
+      d.dst_ld = g.ld;
+      d.nrows = g.nrows;
+      d.ncols = f.cN;
+      d.tri = 0;
+      rd_rows.push_back(rp.add(by[q]));
+      rd.push_back(d);
+      maxcols = std::max(maxcols, f.cN);
+      C[g.owner].groups.push_back((int)G.size());
+      G.push_back(std::move(g));
+    }
+  }
+  int* drp = upload(rp.v);
+  for (size_t i = 0; i < rd.size(); ++i) rd[i].rows = drp + rd_rows[i];
+  launch_rowcopy<T>(upload(rd), (int)rd.size(), maxcols, st);
+  ++launches_;
+  timer_end();
+}
+
+// ---- interface scaling (Section 2.4) -----------------------------------------
+template <typename T>
+void Factorizer<T>::scale_all() {
+  timer_begin(PH_SCALE);
+  std::vector<int> ifaces(live.begin(), live.end());
+  IntPool pool;
+  std::vector<GatherDesc> gd;
+  std::vector<size_t> gd_map;
+  std::vector<QRDesc> qd;
+  std::vector<ExtractDesc> ed;
+  std::vector<T*> Rpp(P.clusters.size(), nullptr);
+  int maxc = 0;
+  int* d_flags = static_cast<int*>(H.arena.alloc(std::max<size_t>(1, ifaces.size()) * sizeof(int)));
+  struct SF {
+    int p;
+    T* F;
+    int64_t ld;
+    int m, n, cs;
+    std::vector<int> nb, cols;
+  };
+  std::vector<SF> sf;
+  for (size_t i = 0; i < ifaces.size(); ++i) {
+    SF f;
+    f.p = ifaces[i];
+    std::vector<int> u;
+    for (int g : C[f.p].groups) u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    u.erase(std::remove(u.begin(), u.end(), f.p), u.end());
+    f.nb = u;
+    f.cols = C[f.p].slots;
+    std::vector<int> ns = slots_of(f.nb);
+    f.cols.insert(f.cols.end(), ns.begin(), ns.end());
+    f.cs = (int)C[f.p].slots.size();
+    f.n = (int)f.cols.size();
+    f.m = 0;
+    for (int g : C[f.p].groups) f.m += G[g].nrows;
+    if (f.m < f.cs) throw Error(SPAQR_EARG, "internal: interface with fewer rows than columns");
+    f.ld = pad(f.m);
+    f.F = talloc(f.ld * f.n);
+    int64_t row0 = 0;
+    for (int g : C[f.p].groups) {
+      GatherDesc d{};
+      d.src = G[g].data;
+      d.dst = f.F;
+      d.src_ld = G[g].ld;
+      d.dst_ld = f.ld;
+      d.row0 = row0;
+      d.nrows = G[g].nrows;
+      d.ncols = f.n;
+      gd_map.push_back(pool.add(colmap(G[g], f.cols, false)));
+      gd.push_back(d);
+      row0 += G[g].nrows;
+    }
+    maxc = std::max(maxc, f.n);
+    QRDesc q{};
+    q.A = f.F;
+    q.tau = talloc(f.cs);
+    q.lda = f.ld;
+    q.m = f.m;
+    q.n = f.n;
+    q.k = f.cs;
+    qd.push_back(q);
+    T* R = talloc((int64_t)f.cs * f.cs);
+    Rpp[f.p] = R;
+    ExtractDesc e{};
+    e.A = f.F;
+    e.R = R;
+    e.flag = d_flags + i;
+    e.lda = f.ld;
+    e.ldr = f.cs;
+    e.c = f.cs;
+    ed.push_back(e);
+    flops_[PH_SCALE] += qr_flops(f.m, f.cs) + 4.0 * f.m * f.cs * (f.n - f.cs) - 2.0 * f.cs * f.cs * (f.n - f.cs);
+    bytes_[PH_SCALE] += 2.0 * sizeof(T) * f.m * f.n;
+    sf.push_back(std::move(f));
+  }
+  int* dpool = upload(pool.v);
+  for (size_t i = 0; i < gd.size(); ++i) gd[i].colmap = dpool + gd_map[i];
+  launch_gather<T>(upload(gd), (int)gd.size(), maxc, st);
+  ++launches_;
+  for (auto& f : sf) dump_front("scale", f.p, f.F, f.ld, f.m, f.n, f.cols);
+  run_qr(qd);
+  launch_extract<T>(upload(ed), (int)ed.size(), st);
+  ++launches_;
+  for (auto& f : sf) {
+    record_op(1, PH_SCALE, Rpp[f.p], nullptr, f.cs, f.cs, 0, C[f.p].slots, {});
+    for (int g : C[f.p].groups) kill_group(g);
+    C[f.p].groups.clear();
+    RG p1;
+    p1.owner = f.p;
+    p1.data = f.F;
+    p1.ld = f.ld;
+    p1.nrows = f.cs;
+    p1.slots = f.cols;
+    p1.clus = f.nb;
+    p1.clus.insert(std::lower_bound(p1.clus.begin(), p1.clus.end(), f.p), f.p);
+    p1.role = 1;
+    C[f.p].groups.push_back((int)G.size());
+    G.push_back(std::move(p1));
+    if (f.m > f.cs && f.n > f.cs) {
+      RG p2;
+      p2.owner = f.p;
+      p2.data = f.F + f.cs + (int64_t)f.cs * f.ld;
+      p2.ld = f.ld;
+      p2.nrows = f.m - f.cs;
+      p2.slots.assign(f.cols.begin() + f.cs, f.cols.end());
+      p2.clus = f.nb;
+      p2.role = 2;
+      C[f.p].groups.push_back((int)G.size());
+      G.push_back(std::move(p2));
+    }
+  }
+  // right scaling of every column block by R_qq^-1
+  IntPool tp;
+  std::vector<TrsmDesc> td;
+  std::vector<size_t> td_map;
+  for (int g : live_groups()) {
+    RG& gr = G[g];
+    for (int q : gr.clus) {
+      if (gr.role == 1 && gr.owner == q) continue;
+      TrsmDesc d{};
+      d.B = gr.data;
+      d.R = Rpp[q];
+      d.ldb = gr.ld;
+      d.ldr = (int64_t)C[q].slots.size();
+      d.nrows = gr.nrows;
+      d.c = (int)C[q].slots.size();
+      td_map.push_back(tp.add(colmap(gr, C[q].slots, true)));
+      td.push_back(d);
+      flops_[PH_SCALE] += (double)gr.nrows * d.c * d.c;
+      bytes_[PH_SCALE] += 2.0 * sizeof(T) * gr.nrows * d.c;
+    }
+  }
+  int* dtp = upload(tp.v);
+  for (size_t i = 0; i < td.size(); ++i) td[i].colmap = dtp + td_map[i];
+  launch_trsm<T>(upload(td), (int)td.size(), st);
+  ++launches_;
+  timer_end();
+  // rank-deficiency flags are read together with the step-1 ranks
+  flags_ = d_flags;
+  nflags_ = (int)ifaces.size();
+}
+
+// ---- sparsification step 1 (Section 2.5.1) -----------------------------------
+template <typename T>
+void Factorizer<T>::step1_all() {
+  timer_begin(PH_SPARSIFY);
+  std::vector<int> who;
+  for (int p : live)
+    for (int g : C[p].groups)
+      if (G[g].role == 2) who.push_back(g);
+  int* d_rank = static_cast<int*>(H.arena.alloc(std::max<size_t>(1, who.size()) * sizeof(int)));
+  std::vector<PQRDesc> pd;
+  for (size_t i = 0; i < who.size(); ++i) {
+    RG& gr = G[who[i]];
+    PQRDesc d{};
+    d.A = gr.data;
+    d.n = (int)gr.slots.size();
+    d.m = gr.nrows;
+    d.lda = gr.ld;
+    d.work = static_cast<double*>(H.arena.alloc(3 * std::max(1, d.n) * sizeof(double)));
+    d.rank_out = d_rank + i;
+    d.forced = next_forced();
+    d.noise = kNoiseRank * unit_roundoff<T>();
+    pd.push_back(d);
+  }
+  launch_pqr<T>(upload(pd), (int)pd.size(), eps_, st);
+  ++launches_;
+  const size_t nr = std::max<size_t>(1, who.size());
+  int* h = static_cast<int*>(H.stage.alloc((nr + nflags_ + 1) * sizeof(int)));
+  SPAQR_HIP(hipMemcpyAsync(h, d_rank, nr * sizeof(int), hipMemcpyDeviceToHost, st));
+  if (nflags_ > 0)
+    SPAQR_HIP(hipMemcpyAsync(h + nr, flags_, nflags_ * sizeof(int), hipMemcpyDeviceToHost, st));
+  sync();
+  for (int i = 0; i < nflags_; ++i)
+    if (h[nr + i]) throw Error(SPAQR_ERANK, "a scaling block is numerically rank deficient");
+  for (size_t i = 0; i < who.size(); ++i) {
+    const int r = h[i];
+    RG& gr = G[who[i]];
+    H.ranks.push_back(r);
+    const double m = gr.nrows, n = (double)gr.slots.size();
+    flops_[PH_SPARSIFY] += 4 * m * n * r - 2.0 * r * r * (m + n) + 4.0 * r * r * r / 3 + 2 * m * n;
+    bytes_[PH_SPARSIFY] += sizeof(T) * (2 * m * n);
+    gr.nrows = r;
+    if (r == 0) {
+      auto& lst = C[gr.owner].groups;
+      lst.erase(std::remove(lst.begin(), lst.end(), who[i]), lst.end());
+      kill_group(who[i]);
+    }
+  }
+  timer_end();
+}
+
+// ---- sparsification step 2 (Section 2.5.2) -----------------------------------
+template <typename T>
+void Factorizer<T>::step2_round(const std::vector<int>& sel) {
+  timer_begin(PH_SPARSIFY);
+  struct S2 {
+    int p, p1, cp, K;
+    std::vector<int> blocks, others, oslots, pslots;
+    T* Cb;
+    int64_t ldc;
+    T* V;
+    T* tau;
+  };
+  std::vector<S2> ss(sel.size());
+  IntPool pool;
+  std::vector<GatherDesc> gd;
+  std::vector<size_t> gd_map;
+  std::vector<PQRDesc> pd;
+  std::vector<ScatterDesc> sd;
+  std::vector<size_t> sd_map;
+  int* d_rank = static_cast<int*>(H.arena.alloc(std::max<size_t>(1, sel.size()) * sizeof(int)));
+  int maxc = 0;
+  const std::vector<int> lg = live_groups();
+  for (size_t i = 0; i < sel.size(); ++i) {
+    S2& s = ss[i];
+    s.p = sel[i];
+    s.p1 = -1;
+    for (int g : C[s.p].groups)
+      if (G[g].role == 1) s.p1 = g;
+    if (s.p1 < 0) throw Error(SPAQR_EARG, "internal: interface without scaled rows");
+    for (int g : lg)
+      if (g != s.p1 && has(G[g].clus, s.p)) s.blocks.push_back(g);
+    for (int c : G[s.p1].clus)
+      if (c != s.p) s.others.push_back(c);
+    s.oslots = slots_of(s.others);
+    s.pslots = C[s.p].slots;
+    s.cp = (int)s.pslots.size();
+    s.K = (int)s.oslots.size();
+    for (int g : s.blocks) s.K += G[g].nrows;
+    s.ldc = pad(s.cp);
+    s.Cb = talloc(s.ldc * std::max(1, s.K));
+    s.V = talloc((int64_t)s.cp * std::max(1, std::min(s.cp, s.K)));
+    s.tau = talloc(std::max(1, std::min(s.cp, s.K)));
+    int64_t col0 = 0;
+    for (int g : s.blocks) {
+      const std::vector<int> cm = colmap(G[g], s.pslots, true);
+      const size_t o = pool.add(cm);
+      GatherDesc d{};
+      d.src = G[g].data;
+      d.dst = s.Cb;
+      d.src_ld = G[g].ld;
+      d.dst_ld = s.ldc;
+      d.row0 = 0;
+      d.col0 = col0;
+      d.nrows = G[g].nrows;
+      d.ncols = s.cp;
+      d.transpose = 1;
+      gd_map.push_back(o);
+      gd.push_back(d);
+      ScatterDesc w{};
+      w.C = s.Cb;
+      w.dst = G[g].data;
+      w.rank = d_rank + i;
+      w.ldc = s.ldc;
+      w.ld = G[g].ld;
+      w.col0 = col0;
+      w.nrows = G[g].nrows;
+      w.ncols = s.cp;
+      w.transpose = 1;
+      sd_map.push_back(o);
+      sd.push_back(w);
+      col0 += G[g].nrows;
+    }
+    {
+      const size_t o = pool.add(colmap(G[s.p1], s.oslots, true));
+      GatherDesc d{};
+      d.src = G[s.p1].data;
+      d.dst = s.Cb;
+      d.src_ld = G[s.p1].ld;
+      d.dst_ld = s.ldc;
+      d.row0 = 0;
+      d.col0 = col0;
+      d.nrows = s.cp;
+      d.ncols = (int)s.oslots.size();
+      gd_map.push_back(o);
+      gd.push_back(d);
+      ScatterDesc w{};
+      w.C = s.Cb;
+      w.dst = G[s.p1].data;
+      w.rank = d_rank + i;
+      w.ldc = s.ldc;
+      w.ld = G[s.p1].ld;
+      w.col0 = col0;
+      w.nrows = s.cp;
+      w.ncols = (int)s.oslots.size();
+      sd_map.push_back(o);
+      sd.push_back(w);
+      const size_t oi = pool.add(colmap(G[s.p1], s.pslots, true));
+      ScatterDesc idw{};
+      idw.dst = G[s.p1].data;
+      idw.rank = d_rank + i;
+      idw.ld = G[s.p1].ld;
+      idw.identity = 1;
+      sd_map.push_back(oi);
+      sd.push_back(idw);
+    }
+    maxc = std::max(maxc, std::max(s.cp, (int)s.oslots.size()));
+    PQRDesc q{};
+    q.A = s.Cb;
+    q.V = s.V;
+    q.tau = s.tau;
+    q.lda = s.ldc;
+    q.m = s.cp;
+    q.n = s.K;
+    q.work = static_cast<double*>(H.arena.alloc(3 * std::max(1, s.K) * sizeof(double)));
+    q.rank_out = d_rank + i;
+    q.forced = next_forced();
+    q.noise = kNoiseRank * unit_roundoff<T>();
+    pd.push_back(q);
+  }
+  int* dpool = upload(pool.v);
+  for (size_t i = 0; i < gd.size(); ++i) gd[i].colmap = dpool + gd_map[i];
+  for (size_t i = 0; i < sd.size(); ++i) sd[i].colmap = dpool + sd_map[i];
+  launch_gather<T>(upload(gd), (int)gd.size(), maxc, st);
+  launch_pqr<T>(upload(pd), (int)pd.size(), eps_, st);
+  launch_scatter<T>(upload(sd), (int)sd.size(), st);
+  launches_ += 3;
+  int* h = static_cast<int*>(H.stage.alloc(std::max<size_t>(1, sel.size()) * sizeof(int)));
+  SPAQR_HIP(hipMemcpyAsync(h, d_rank, sel.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+  sync();
+  timer_end();
+  for (size_t i = 0; i < ss.size(); ++i) {
+    S2& s = ss[i];
+    const int r = h[i];
+    H.ranks.push_back(r);
+    const double m = s.cp, n = s.K;
+    flops_[PH_SPARSIFY] += 4 * m * n * r - 2.0 * r * r * (m + n) + 4.0 * r * r * r / 3 + 2 * m * n;
+    bytes_[PH_SPARSIFY] += sizeof(T) * (2 * m * n);
+    record_op(2, PH_SPARSIFY, s.V, s.tau, s.cp, s.cp, r, s.pslots, {});
+    G[s.p1].nrows = r;
+    C[s.p].slots.resize(r);
+    if (r == 0) vanish(s.p);
+  }
+}
+
+// An interface left without coarse columns: its rows move to the cluster
+// holding most of their squared norm (the rule of Section 2.3).
+template <typename T>
+void Factorizer<T>::vanish(int p) {
+  C[p].alive = false;
+  live.erase(p);
+  for (int g : live_groups()) {
+    auto& cl = G[g].clus;
+    auto it = std::lower_bound(cl.begin(), cl.end(), p);
+    if (it != cl.end() && *it == p) cl.erase(it);
+  }
+  std::vector<int> mine = C[p].groups;
+  C[p].groups.clear();
+  for (int g : mine) {
+    if (G[g].role == 1 || G[g].nrows == 0) {
+      kill_group(g);
+      continue;
+    }
+    auto& cl = G[g].clus;
+    cl.erase(std::remove(cl.begin(), cl.end(), p), cl.end());
+    reassign_group_rows(g);
+  }
+}
+
+template <typename T>
+void Factorizer<T>::reassign_group_rows(int gi) {
+  RG src = G[gi];
+  kill_group(gi);
+  if (src.clus.empty() || src.nrows == 0) return;
+  std::vector<int> cm, off{0};
+  for (int c : src.clus) {
+    std::vector<int> m = colmap(src, C[c].slots, true);
+    cm.insert(cm.end(), m.begin(), m.end());
+    off.push_back((int)cm.size());
+  }
+  IntPool pool;
+  const size_t ocm = pool.add(cm), oof = pool.add(off);
+  int* dp = upload(pool.v);
+  int* d_owner = static_cast<int*>(H.arena.alloc(src.nrows * sizeof(int)));
+  OwnerDesc d{};
+  d.A = src.data;
+  d.colmap = dp + ocm;
+  d.cl_off = dp + oof;
+  d.owner = d_owner;
+  d.lda = src.ld;
+  d.nrows = src.nrows;
+  d.ncl = (int)src.clus.size();
+  launch_owner<T>(upload(std::vector<OwnerDesc>{d}), 1, st);
+  int* h = static_cast<int*>(H.stage.alloc(src.nrows * sizeof(int)));
+  SPAQR_HIP(hipMemcpyAsync(h, d_owner, src.nrows * sizeof(int), hipMemcpyDeviceToHost, st));
+  sync();
+  std::vector<std::vector<int>> by(src.clus.size());
+  for (int r = 0; r < src.nrows; ++r) by[h[r]].push_back(r);
+  IntPool rp;
+  std::vector<RowCopyDesc> rd;
+  std::vector<size_t> rmap;
+  for (size_t q = 0; q < by.size(); ++q) {
+    if (by[q].empty()) continue;
+    RG g;
+    g.owner = src.clus[q];
+    g.nrows = (int)by[q].size();
+    g.ld = pad(g.nrows);
+    g.data = talloc(g.ld * (int64_t)src.slots.size());
+    g.slots = src.slots;
+    g.clus = src.clus;
+    RowCopyDesc c{};
+    c.src = src.data;
+    c.dst = g.data;
+    c.src_ld = src.ld;
+    c.dst_ld = g.ld;
+    c.nrows = g.nrows;
+    c.ncols = (int)src.slots.size();
+    rmap.push_back(rp.add(by[q]));
+    rd.push_back(c);
+    C[g.owner].groups.push_back((int)G.size());
+    G.push_back(std::move(g));
+  }
+  int* drp = upload(rp.v);
+  for (size_t i = 0; i < rd.size(); ++i) rd[i].rows = drp + rmap[i];
+  launch_rowcopy<T>(upload(rd), (int)rd.size(), (int)src.slots.size(), st);
+  launches_ += 2;
+}
+
+// ---- merge (Section 2.6) ------------------------------------------------------
+template <typename T>
+void Factorizer<T>::merge(int m) {
+  std::vector<int> remap(P.clusters.size(), -1);
+  bool any = false;
+  for (const NDNode& S : P.nodes) {
+    if (S.leaf() || S.level >= m) continue;
+    const int fin = std::max(S.level, P.depth - 1);
+    const int cur = std::min(std::max(S.level, m - 1), fin);
+    const int tgt = std::min(std::max(S.level, m - 2), fin);
+    if (tgt >= cur) continue;
+    for (int pc : S.pieces[tgt - S.level]) {
+      RC& par = C[pc];
+      par.slots.clear();
+      par.groups.clear();
+      for (int k : P.clusters[pc].children) {
+        if (!C[k].alive) continue;
+        par.slots.insert(par.slots.end(), C[k].slots.begin(), C[k].slots.end());
+        for (int g : C[k].groups) {
+          G[g].owner = pc;
+          par.groups.push_back(g);
+        }
+        C[k].groups.clear();
+        C[k].alive = false;
+        live.erase(k);
+        remap[k] = pc;
+        any = true;
+      }
+      par.alive = !par.slots.empty();
+      if (par.alive) live.insert(pc);
+    }
+  }
+  if (!any) return;
+  for (int g : live_groups()) {
+    auto& cl = G[g].clus;
+    for (int& c : cl)
+      if (remap[c] >= 0) c = remap[c];
+    std::sort(cl.begin(), cl.end());
+    cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
+  }
+}
+
+// ---- device op lists for the apply sweeps ------------------------------------
+template <typename T>
+void Factorizer<T>::build_apply() {
+  H.batches.clear();
+  size_t i = 0;
+  while (i < H.ops.size()) {
+    size_t j = i;
+    while (j < H.ops.size() && H.ops[j].level == H.ops[i].level && H.ops[j].phase == H.ops[i].phase &&
+           H.ops[j].round == H.ops[i].round)
+      ++j;
+    IntPool pool;
+    std::vector<size_t> o1, o2;
+    for (size_t k = i; k < j; ++k) {
+      o1.push_back(pool.add(H.ops[k].s1));
+      o2.push_back(pool.add(H.ops[k].s2));
+    }
+    int* dp = upload(pool.v);
+    std::vector<ApplyOp> ao;
+    int mx = 0;
+    for (size_t k = i; k < j; ++k) {
+      OpRec& o = H.ops[k];
+      o.d_s1 = dp + o1[k - i];
+      o.d_s2 = dp + o2[k - i];
+      ApplyOp a{};
+      a.R = o.R;
+      a.tau = o.tau;
+      a.s1 = o.d_s1;
+      a.s2 = o.d_s2;
+      a.ld = o.ld;
+      a.n1 = o.n1;
+      a.n2 = o.n2;
+      a.kind = o.kind;
+      ao.push_back(a);
+      mx = std::max(mx, o.n1);
+    }
+    ApplyBatch b;
+    b.d_ops = upload(ao);
+    b.n = (int)ao.size();
+    b.max_n1 = mx;
+    H.batches.push_back(b);
+    i = j;
+  }
+}
+
+template <typename T>
+void Factorizer<T>::run() {
+  const double t0 = now_s();
+  init_groups();
+  double merge_s = 0.0;
+  for (int m = P.depth; m >= 1; --m) {
+    level_ = m;
+    eliminate_level(m);
+    if (m >= 2 && m <= P.depth - P.skip && !live.empty()) {
+      scale_all();
+      step1_all();
+      std::vector<int> pending(live.begin(), live.end());
+      round_ = 0;
+      while (!pending.empty()) {
+        auto p1 = [&](int p) {
+          for (int g : C[p].groups)
+            if (G[g].role == 1) return g;
+          throw Error(SPAQR_EARG, "internal: interface without scaled rows");
+        };
+        std::vector<int> sel, rest;
+        for (int p : pending) {
+          bool ok = true;
+          for (int q : sel)
+            if (has(G[p1(p)].clus, q) || has(G[p1(q)].clus, p)) ok = false;
+          (ok ? sel : rest).push_back(p);
+        }
+        step2_round(sel);
+        pending.swap(rest);
+        ++round_;
+      }
+    }
+    const double tm = now_s();
+    merge(m);
+    merge_s += now_s() - tm;
+  }
+  if (!live.empty()) throw Error(SPAQR_EARG, "internal: clusters left after the root level");
+  if (forced_ && fpos_ != nforced_) throw Error(SPAQR_EARG, "forced rank list not fully used");
+  build_apply();
+  sync();
+  double ph[5] = {0, 0, 0, 0, merge_s};
+  for (auto& t : timers_) {
+    float ms = 0.f;
+    SPAQR_HIP(hipEventElapsedTime(&ms, t.second.first, t.second.second));
+    ph[t.first] += ms * 1e-3;
+    (void)hipEventDestroy(t.second.first);
+    (void)hipEventDestroy(t.second.second);
+  }
+  timers_.clear();
+  spaqr_stats& S = H.stats;
+  S.levels = P.depth;
+  S.num_ops = (int)H.ops.size();
+  S.num_ranks = (int)H.ranks.size();
+  S.launches = launches_;
+  S.syncs = syncs_;
+  int64_t mem = 0;
+  for (auto& o : H.ops) {
+    if (o.kind == 0)
+      mem += (int64_t)o.n1 * (o.n1 + 1) / 2 + (int64_t)o.n1 * o.n2;
+    else if (o.kind == 1)
+      mem += (int64_t)o.n1 * (o.n1 + 1) / 2;
+    else
+      mem += (int64_t)o.n1 * o.n2;
+  }
+  S.mem_factor = mem;
+  S.device_bytes = (int64_t)(H.arena.capacity() + H.plan_bytes);
+  for (int k = 0; k < 5; ++k) {
+    S.flops[k] = flops_[k];
+    S.bytes[k] = bytes_[k];
+    S.phase_seconds[k] = ph[k];
+  }
+  S.factor_seconds = now_s() - t0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// entry points used by the C-ABI
+// ---------------------------------------------------------------------------
+
+void factorize(Handle& H, double eps, const int* forced, int nforced) {
+  if (!(eps >= 0.0)) throw Error(SPAQR_EARG, "eps must be >= 0");
+  H.ensure_device();
+  H.factored = false;
+  SPAQR_HIP(hipStreamSynchronize(H.stream));
+  H.arena.reset();
+  H.stage.reset();
+  H.ops.clear();
+  H.batches.clear();
+  H.ranks.clear();
+  const int top_cols = 0;
+  H.stats = spaqr_stats{};
+  H.stats.top_cols = top_cols;
+  H.precision = H.opt.precision;
+  if (H.precision == SPAQR_FP32_FACTOR)
+    Factorizer<float>(H, eps, forced, nforced).run();
+  else
+    Factorizer<double>(H, eps, forced, nforced).run();
+  H.factored = true;
+}
+
+void apply_op(Handle& H, bool transpose, double* x) {
+  const int nb = (int)H.batches.size();
+  for (int k = 0; k < nb; ++k) {
+    const ApplyBatch& b = H.batches[transpose ? k : nb - 1 - k];
+    if (H.precision == SPAQR_FP32_FACTOR)
+      launch_apply_batch<float>(b.d_ops, b.n, b.max_n1, transpose, x, H.stream);
+    else
+      launch_apply_batch<double>(b.d_ops, b.n, b.max_n1, transpose, x, H.stream);
+  }
+}
+
+}  // namespace spaqr

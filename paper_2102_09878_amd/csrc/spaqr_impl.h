@@ -1,0 +1,281 @@
+// Internal declarations of libspaqr: host plan, runtime state, kernel
+// descriptors and launchers.  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <set>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/spaqr.h"
+
+namespace spaqr {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SPAQR_HIP(call)                                                                 \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::spaqr::Error(SPAQR_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Analysis (host only)
+// ---------------------------------------------------------------------------
+
+struct NDNode {
+  int level = 0;
+  int64_t path = 0;
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  int axis = -1;  // -1: leaf
+  int t = -1;     // first separator plane
+  int child[2] = {-1, -1};
+  int parent = -1;
+  int rank = 0;
+  // cluster ids of the pieces at granularity level + i
+  std::vector<std::vector<int>> pieces;
+  bool leaf() const { return axis < 0; }
+};
+
+struct Cluster {
+  int64_t key0 = 0, key1 = 0;  // (separator elimination rank, lower-corner cell)
+  int sep = -1;                // ND node index (rank)
+  int gran = 0;
+  int lo[3], hi[3];
+  int parent = -1;
+  std::vector<int> children;   // cluster ids at gran + 1, in id order
+  std::vector<int> cells;      // finest clusters: cells ascending
+  int finest_index = -1;
+};
+
+struct InitGroup {
+  int owner;                   // cluster id
+  std::vector<int> rows;       // ascending
+  std::vector<int> clus;       // touched clusters, id order
+  int64_t offset;              // element offset inside the initial-group region
+  int64_t ld;
+  int width;
+};
+
+struct Plan {
+  int64_t M = 0, N = 0, nnz = 0;
+  int grid[3] = {1, 1, 1};
+  int depth = 0, skip = 0, w = 2;
+  std::vector<int64_t> row_ptr;
+  std::vector<int32_t> col_idx;
+  std::vector<double> vals, D, ahat;
+  std::vector<NDNode> nodes;        // indexed by elimination rank
+  std::vector<Cluster> clusters;    // every granularity; id order == key order
+  std::vector<int> finest;          // finest cluster ids, id order
+  std::vector<int> col_cluster;     // finest cluster id of each column
+  std::vector<int> row_owner;       // finest cluster id of each row
+  std::vector<InitGroup> init_groups;
+  std::vector<int64_t> init_dst;    // per CSR entry: element offset of its slot in the initial groups
+  int64_t init_elems = 0;
+  // A^T in CSR (column-major view of A) for the transposed products
+  std::vector<int64_t> at_ptr;
+  std::vector<int32_t> at_idx;
+  std::vector<int64_t> at_src;      // CSR entry index of each A^T entry
+  double normA = 0.0;
+};
+
+void analyze_plan(Plan& P, const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
+                  int64_t M, int64_t N, const spaqr_options& opt);
+void rescale_values(Plan& P, const double* vals);
+
+// ---------------------------------------------------------------------------
+// Device memory
+// ---------------------------------------------------------------------------
+
+// Bump allocator over large device chunks; reset() keeps the chunks.
+class Arena {
+ public:
+  ~Arena();
+  void* alloc(size_t bytes);
+  void reset();
+  void release();
+  size_t capacity() const;
+  size_t used() const { return used_total_; }
+
+ private:
+  struct Chunk {
+    char* ptr;
+    size_t size;
+    size_t off;
+  };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0;
+  size_t used_total_ = 0;
+};
+
+// Bump allocator over pinned host memory, used to stage descriptor uploads.
+class Staging {
+ public:
+  ~Staging();
+  void* alloc(size_t bytes);
+  void reset();
+  void release();
+
+ private:
+  struct Chunk {
+    char* ptr;
+    size_t size;
+    size_t off;
+  };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel descriptors (plain structs copied to the device)
+// ---------------------------------------------------------------------------
+
+// dst[(row0 + r) + (col0 + c) * dst_ld] = colmap[c] >= 0 ? src[r + colmap[c] * src_ld] : 0
+// (transpose == 1: dst[c + (col0 + r) * dst_ld] instead).
+struct GatherDesc {
+  const void* src;
+  void* dst;
+  const int* colmap;
+  int64_t src_ld, dst_ld, row0, col0;
+  int nrows, ncols, transpose, pad_;
+};
+
+// Householder QR of the leading k columns of A (m x n, ld lda); the
+// reflectors are applied to all n columns.  tau[min(m,k)].
+struct QRDesc {
+  void* A;
+  void* tau;
+  int64_t lda;
+  int m, n, k, pad_;
+};
+
+// Column-pivoted QR of A (m x n), in place, columns not swapped; first
+// `rank` rows of A become the first rows of Q^T A with zeros below the
+// diagonal of pivot columns.  V (ld m) and tau receive the reflectors when
+// non-null.  rank_out[0] receives the rank.
+// Rank rule: stop at the first step i with |R_ii| <= noise * ||A||_F (the
+// numerical rank), then at |R_ii| < eps |R_00|, or at i == forced when
+// forced >= 0.
+struct PQRDesc {
+  void* A;
+  void* V;
+  void* tau;
+  double* work;      // 3 * n doubles (norms, reference norms, done flags)
+  int* rank_out;
+  int* piv_out;      // pivot column per step (min(m,n))
+  int64_t lda;
+  double noise;
+  int m, n, forced, pad_;
+};
+
+// B <- B R^-1 on the columns colmap[0..c) of a group block (nrows x ., ld).
+struct TrsmDesc {
+  void* B;
+  const void* R;
+  const int* colmap;
+  int64_t ldb, ldr;
+  int nrows, c;
+};
+
+// owner[i] = argmax over clusters q of sum_{c in q} A[i, colmap[c]]^2 for
+// i < nrows, cluster q owning colmap entries [cl_off[q], cl_off[q+1]);
+// first maximum wins.  nrows_dev (when set) holds the row count on the
+// device, e.g. the rank just chosen by a rank-revealing QR.
+struct OwnerDesc {
+  const void* A;
+  const int* colmap;
+  const int* cl_off;
+  int* owner;
+  const int* nrows_dev;
+  int64_t lda;
+  int nrows, ncl;
+};
+
+// dst[i + c * dst_ld] = src[rows[i] + c * src_ld] for c < ncols, zeroed where
+// c < rows[i] - tri_base when tri != 0 (upper-trapezoidal rows).
+struct RowCopyDesc {
+  const void* src;
+  void* dst;
+  const int* rows;
+  int64_t src_ld, dst_ld;
+  int nrows, ncols, tri, tri_base;
+};
+
+// Copy upper triangle of A (c x c, lda) to R (ldr), then set the block to I.
+// flag[0] = 1 if min |R_ii| <= 64 u ||R||_F.
+struct ExtractDesc {
+  void* A;
+  void* R;
+  int* flag;
+  int64_t lda, ldr;
+  int c, pad_;
+};
+
+// Step-2 write-back.  For transposed pieces: dst[r + colmap[i] * ld] =
+// C[i + (col0 + r) * ldc] for i < rank, r < nrows.  For the scaled rows
+// (transpose == 0): dst[i + colmap[c] * ld] = C[i + (col0 + c) * ldc] for
+// i < rank, c < ncols; identity == 1 writes delta_ij on colmap instead.
+struct ScatterDesc {
+  const void* C;
+  void* dst;
+  const int* colmap;
+  const int* rank;
+  int64_t ldc, ld, col0;
+  int nrows, ncols, transpose, identity;
+};
+
+// ---------------------------------------------------------------------------
+// Apply descriptors (W^-1 / W^-T sweeps)
+// ---------------------------------------------------------------------------
+
+struct ApplyOp {
+  const void* R;       // eliminate / scale: triangular factor; sparsify: reflectors
+  const void* tau;     // sparsify
+  const int* s1;       // slots of the cluster
+  const int* s2;       // slots of the neighbours (eliminate)
+  int64_t ld;
+  int n1, n2;          // eliminate: c_s, c_N; scale: c_p, 0; sparsify: c_p, r
+  int kind, pad_;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (kernels.hip, apply.hip)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+void launch_gather(const GatherDesc* d_desc, int n, int max_cols, hipStream_t s);
+template <typename T>
+void launch_scatter_csr(T* base, const int64_t* dst, const double* ahat, int64_t nnz, hipStream_t s);
+template <typename T>
+void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h_desc, double* tbuf, hipStream_t s,
+               int* launches);
+template <typename T>
+void launch_pqr(const PQRDesc* d_desc, int n, double eps, hipStream_t s);
+template <typename T>
+void launch_trsm(const TrsmDesc* d_desc, int n, hipStream_t s);
+template <typename T>
+void launch_owner(const OwnerDesc* d_desc, int n, hipStream_t s);
+template <typename T>
+void launch_rowcopy(const RowCopyDesc* d_desc, int n, int max_cols, hipStream_t s);
+template <typename T>
+void launch_extract(const ExtractDesc* d_desc, int n, hipStream_t s);
+template <typename T>
+void launch_scatter(const ScatterDesc* d_desc, int n, hipStream_t s);
+
+template <typename T>
+void launch_apply_batch(const ApplyOp* d_ops, int n, int max_n1, bool transpose, double* x,
+                        hipStream_t s);
+
+void launch_spmv(const int64_t* ptr, const int32_t* idx, const double* val, const double* x,
+                 double* y, int64_t rows, hipStream_t s);
+void launch_spmv_at(const int64_t* ptr, const int32_t* idx, const int64_t* src, const double* val,
+                    const double* x, double* y, int64_t cols, hipStream_t s);
+
+}  // namespace spaqr

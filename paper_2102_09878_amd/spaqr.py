@@ -1,0 +1,287 @@
+"""Thin ctypes binding of libspaqr (the C-ABI declared in include/spaqr.h).
+
+Argument marshalling only: every step of the factorization and of the
+solvers runs in the library's HIP kernels.  Device vectors are passed as
+torch tensors on the GPU (FP64, contiguous); PyTorch is used for device
+memory only.  The binding fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("SPAQR_LIB", os.path.join(_HERE, "libspaqr.so"))
+
+OK, NOCONV = 0, 1
+EARG, ESTATE, ERANK, EHIP, ENOMEM = -1, -2, -3, -4, -5
+FP64, FP32_FACTOR = 0, 1
+WINV, WINVT = 0, 1
+
+EXPORTS = ["spaqr_analyze", "spaqr_get_ordering", "spaqr_set_values", "spaqr_factorize",
+           "spaqr_factorize_forced", "spaqr_apply", "spaqr_apply_op", "spaqr_cgls", "spaqr_factor_stats",
+           "spaqr_get_ranks", "spaqr_get_op", "spaqr_destroy", "spaqr_last_error"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("nd_depth", ctypes.c_int32), ("sparsify_skip", ctypes.c_int32),
+                ("grid", ctypes.c_int32 * 3), ("sep_width", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class CglsInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("residual", ctypes.c_double),
+                ("paper_residual", ctypes.c_double), ("norm_a", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("num_ops", ctypes.c_int32), ("num_ranks", ctypes.c_int32),
+                ("top_cols", ctypes.c_int32), ("top_rows", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("syncs", ctypes.c_int32), ("pad_", ctypes.c_int32), ("mem_factor", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("flops", ctypes.c_double * 5),
+                ("bytes", ctypes.c_double * 5), ("phase_seconds", ctypes.c_double * 5),
+                ("factor_seconds", ctypes.c_double)]
+
+
+class OpDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n1", ctypes.c_int32), ("n2", ctypes.c_int32),
+                ("round", ctypes.c_int32), ("level", ctypes.c_int32)]
+
+
+PHASES = ("eliminate", "reassign", "scale", "sparsify", "merge")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libspaqr.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libspaqr.so not found at {path}; run `python -m paper_2102_09878_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "spaqr_analyze": [P, P, P, I64, I64, ctypes.POINTER(Options), ctypes.POINTER(P)],
+        "spaqr_get_ordering": [P, P, P],
+        "spaqr_set_values": [P, P],
+        "spaqr_factorize": [P, D],
+        "spaqr_factorize_forced": [P, D, P, I32],
+        "spaqr_apply": [P, P, P],
+        "spaqr_apply_op": [P, I32, P, P],
+        "spaqr_cgls": [P, P, D, I32, P, ctypes.POINTER(CglsInfo)],
+        "spaqr_factor_stats": [P, ctypes.POINTER(Stats)],
+        "spaqr_get_ranks": [P, P, I32, ctypes.POINTER(I32)],
+        "spaqr_get_op": [P, I32, ctypes.POINTER(OpDesc), P, P, P, P],
+        "spaqr_destroy": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.spaqr_last_error.argtypes = [P]
+    lib.spaqr_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class SpaqrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"spaqr error {code}: {msg}")
+        self.code = code
+
+
+def _check(lib, h, rc, allow=(OK,)):
+    if rc not in allow:
+        msg = lib.spaqr_last_error(h)
+        raise SpaqrError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def _ptr(a):
+    """Device pointer of a torch tensor or host pointer of a numpy array."""
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev_f64(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return t
+
+
+# ---- functions with the C-ABI names ----------------------------------------
+
+def spaqr_analyze(row_ptr, col_idx, vals, M, N, grid, nd_depth=0, sparsify_skip=-1, sep_width=0,
+                  precision=FP64, device=0):
+    lib = load()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(vals, dtype=np.float64)
+    g = list(grid) + [1] * (3 - len(grid))
+    opt = Options(nd_depth, sparsify_skip, (ctypes.c_int32 * 3)(*g), sep_width, precision, device, None)
+    h = ctypes.c_void_p()
+    rc = lib.spaqr_analyze(_ptr(rp), _ptr(ci), _ptr(va), int(M), int(N), ctypes.byref(opt), ctypes.byref(h))
+    _check(lib, None, rc)
+    return h
+
+
+def spaqr_get_ordering(h, M, N):
+    lib = load()
+    cp = np.zeros(N, dtype=np.int32)
+    ro = np.zeros(M, dtype=np.int32)
+    _check(lib, h, lib.spaqr_get_ordering(h, _ptr(cp), _ptr(ro)))
+    return cp, ro
+
+
+def spaqr_set_values(h, vals_dev):
+    lib = load()
+    _check(lib, h, lib.spaqr_set_values(h, _ptr(_dev_f64(vals_dev))))
+
+
+def spaqr_factorize(h, eps):
+    lib = load()
+    _check(lib, h, lib.spaqr_factorize(h, float(eps)))
+
+
+def spaqr_factorize_forced(h, eps, ranks):
+    lib = load()
+    r = np.ascontiguousarray(ranks, dtype=np.int32)
+    _check(lib, h, lib.spaqr_factorize_forced(h, float(eps), _ptr(r), int(r.shape[0])))
+
+
+def spaqr_apply(h, b_dev, x_dev):
+    lib = load()
+    _check(lib, h, lib.spaqr_apply(h, _ptr(_dev_f64(b_dev)), _ptr(_dev_f64(x_dev))))
+
+
+def spaqr_apply_op(h, op, in_dev, out_dev):
+    lib = load()
+    _check(lib, h, lib.spaqr_apply_op(h, int(op), _ptr(_dev_f64(in_dev)), _ptr(_dev_f64(out_dev))))
+
+
+def spaqr_cgls(h, b_dev, x_dev, tol=1e-10, max_iter=200):
+    lib = load()
+    info = CglsInfo()
+    rc = lib.spaqr_cgls(h, _ptr(_dev_f64(b_dev)), float(tol), int(max_iter), _ptr(_dev_f64(x_dev)),
+                        ctypes.byref(info))
+    _check(lib, h, rc, allow=(OK, NOCONV))
+    return dict(iters=info.iters, converged=bool(info.converged), residual=info.residual,
+                paper_residual=info.paper_residual, norm_a=info.norm_a, seconds=info.seconds)
+
+
+def spaqr_factor_stats(h):
+    lib = load()
+    s = Stats()
+    _check(lib, h, lib.spaqr_factor_stats(h, ctypes.byref(s)))
+    return dict(levels=s.levels, num_ops=s.num_ops, num_ranks=s.num_ranks, top_cols=s.top_cols,
+                top_rows=s.top_rows, launches=s.launches, syncs=s.syncs, mem_factor=s.mem_factor,
+                device_bytes=s.device_bytes, flops=dict(zip(PHASES, s.flops)),
+                bytes=dict(zip(PHASES, s.bytes)), phase_seconds=dict(zip(PHASES, s.phase_seconds)),
+                factor_seconds=s.factor_seconds)
+
+
+def spaqr_get_ranks(h):
+    lib = load()
+    n = ctypes.c_int32()
+    _check(lib, h, lib.spaqr_get_ranks(h, None, 0, ctypes.byref(n)))
+    out = np.zeros(max(1, n.value), dtype=np.int32)
+    _check(lib, h, lib.spaqr_get_ranks(h, _ptr(out), n.value, ctypes.byref(n)))
+    return out[:n.value].tolist()
+
+
+def spaqr_get_op(h, i):
+    lib = load()
+    d = OpDesc()
+    _check(lib, h, lib.spaqr_get_op(h, int(i), ctypes.byref(d), None, None, None, None))
+    kind, n1, n2 = d.kind, d.n1, d.n2
+    cols = n1 + n2 if kind == 0 else (n1 if kind == 1 else n2)
+    mat = np.zeros((n1, cols))
+    s1 = np.zeros(n1, dtype=np.int32)
+    s2 = np.zeros(max(1, n2 if kind == 0 else 0), dtype=np.int32)
+    tau = np.zeros(max(1, n2 if kind == 2 else 0))
+    _check(lib, h, lib.spaqr_get_op(h, int(i), ctypes.byref(d), _ptr(mat), _ptr(s1), _ptr(s2), _ptr(tau)))
+    out = dict(kind=("elim", "scale", "sparsify")[kind], level=d.level, round=d.round, mat=mat, slots=s1)
+    if kind == 0:
+        out["nslots"] = s2[:n2]
+    if kind == 2:
+        out["tau"] = tau[:n2]
+    return out
+
+
+def spaqr_destroy(h):
+    lib = load()
+    return lib.spaqr_destroy(h)
+
+
+# ---- convenience wrapper ------------------------------------------------------
+
+class Solver:
+    """One least-squares problem: analysis, factor and solves on one GPU."""
+
+    def __init__(self, row_ptr, col_idx, vals, M, N, grid, depth=0, skip=-1, sep_width=0,
+                 precision="fp64", device=0):
+        self.M, self.N = int(M), int(N)
+        prec = {"fp64": FP64, "fp32": FP32_FACTOR}[precision]
+        self.h = spaqr_analyze(row_ptr, col_idx, vals, M, N, grid, depth, skip, sep_width, prec, device)
+
+    @classmethod
+    def from_problem(cls, prob, depth=0, skip=-1, precision="fp64"):
+        return cls(prob.row_ptr, prob.col_idx, prob.vals, prob.M, prob.N, prob.grid, depth, skip,
+                   precision=precision)
+
+    def ordering(self):
+        return spaqr_get_ordering(self.h, self.M, self.N)
+
+    def factorize(self, eps, ranks=None):
+        if ranks is None:
+            spaqr_factorize(self.h, eps)
+        else:
+            spaqr_factorize_forced(self.h, eps, ranks)
+
+    def set_values(self, vals_dev):
+        spaqr_set_values(self.h, vals_dev)
+
+    def cgls(self, b_dev, tol=1e-10, max_iter=200):
+        import torch
+        x = torch.empty(self.N, dtype=torch.float64, device=b_dev.device)
+        info = spaqr_cgls(self.h, b_dev, x, tol, max_iter)
+        return x, info
+
+    def apply(self, b_dev):
+        import torch
+        x = torch.empty(self.N, dtype=torch.float64, device=b_dev.device)
+        spaqr_apply(self.h, b_dev, x)
+        return x
+
+    def apply_op(self, op, v_dev):
+        import torch
+        out = torch.empty_like(v_dev)
+        spaqr_apply_op(self.h, op, v_dev, out)
+        return out
+
+    def stats(self):
+        return spaqr_factor_stats(self.h)
+
+    def ranks(self):
+        return spaqr_get_ranks(self.h)
+
+    def op(self, i):
+        return spaqr_get_op(self.h, i)
+
+    def close(self):
+        if self.h:
+            spaqr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

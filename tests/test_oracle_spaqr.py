@@ -92,7 +92,8 @@ def test_error_decreases_with_eps():
         Ah = p.dense() / an.D[None, :]
         B = Ah @ _winv_dense(f, an.N)
         errs.append(np.linalg.norm(B.T @ B - np.eye(an.N), 2))
-    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] <= 50 * 1e-3 and errs[2] <= 50 * 1e-6
     assert errs[3] <= 1e-12
 
 
