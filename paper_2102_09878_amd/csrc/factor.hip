@@ -335,6 +335,22 @@ class Factorizer {
     std::fclose(fp);
   }
 
+  // Debug hook: SPAQR_DEBUG_SHAPES=1 prints one line per batched launch.
+  template <class D>
+  void log_shapes(const char* what, const std::vector<D>& v) {
+    static const bool on = std::getenv("SPAQR_DEBUG_SHAPES") != nullptr;
+    if (!on || v.empty()) return;
+    int mm = 0, mn = 0;
+    double work = 0;
+    for (auto& d : v) {
+      mm = std::max(mm, d.m);
+      mn = std::max(mn, d.n);
+      work += (double)d.m * d.n;
+    }
+    std::fprintf(stderr, "[spaqr] L%d r%d %-8s count %4zu max_m %5d max_n %6d sum_mn %.3e\n", level_, round_,
+                 what, v.size(), mm, mn, work);
+  }
+
   void ensure_tbuf(size_t n) {
     if (n > tbuf_cap_) {
       tbuf_cap_ = std::max<size_t>(n, 2 * tbuf_cap_);
@@ -342,10 +358,49 @@ class Factorizer {
     }
   }
 
+  // Batched rank-revealing QR: one launch per pivot step until every
+  // matrix has stopped (polled every few steps).
+  void run_pqr(std::vector<PQRDesc>& q) {
+    if (q.empty()) return;
+    int total = 0, kmax = 0, max_m = 1, live_m = 0;
+    std::vector<int2> bmap;
+    for (size_t k = 0; k < q.size(); ++k) {
+      q[k].blk0 = total;
+      q[k].nblk = std::max(1, (q[k].n + PQR_CW - 1) / PQR_CW);
+      for (int c = 0; c < q[k].nblk; ++c) bmap.push_back(make_int2((int)k, c));
+      total += q[k].nblk;
+      kmax = std::max(kmax, std::min(q[k].m, q[k].n));
+      max_m = std::max(max_m, q[k].m);
+      if (std::min(q[k].m, q[k].n) > 0) ++live_m;
+    }
+    const PQRDesc* d = upload(q);
+    const int2* dmap = upload(bmap);
+    auto* states = static_cast<PQRState*>(H.arena.alloc(2 * q.size() * sizeof(PQRState)));
+    auto* parts = static_cast<PQRPart*>(H.arena.alloc(2 * (size_t)total * sizeof(PQRPart)));
+    int* active = upload(std::vector<int>{live_m});
+    int* h_active = static_cast<int*>(H.stage.alloc(sizeof(int)));
+    launch_pqr_init<T>(d, total, states, parts, dmap, st);
+    ++launches_;
+    int steps = 0;
+    while (steps < kmax) {
+      launch_pqr_step<T>(d, total, total, states, parts, dmap, active, steps, eps_, max_m, st);
+      ++launches_;
+      ++steps;
+      if (steps % 16 == 0 && steps < kmax) {
+        SPAQR_HIP(hipMemcpyAsync(h_active, active, sizeof(int), hipMemcpyDeviceToHost, st));
+        sync();
+        if (*h_active == 0) break;
+      }
+    }
+    launch_pqr_finish<T>(d, (int)q.size(), states, steps, st);
+    ++launches_;
+  }
+
   void run_qr(const std::vector<QRDesc>& q) {
     if (q.empty()) return;
     ensure_tbuf(q.size());
     QRDesc* d = upload(q);
+    log_shapes("qr", q);
     launch_qr<T>(d, q, tbuf_, st, &launches_);
   }
 
@@ -564,8 +619,8 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
   timer_begin(PH_REASSIGN);
   int* d_rank = static_cast<int*>(H.arena.alloc(qe.size() * sizeof(int)));
   for (size_t e = 0; e < qe.size(); ++e) qe[e].rank_out = d_rank + e;
-  launch_pqr<T>(upload(qe), (int)qe.size(), eps_, st);
-  ++launches_;
+  log_shapes("reassign", qe);
+  run_pqr(qe);
   // owner of each kept row (Section 2.3: maximum-norm heuristic)
   IntPool op;
   std::vector<OwnerDesc> od;
@@ -823,8 +878,8 @@ void Factorizer<T>::step1_all() {
     d.noise = kNoiseRank * unit_roundoff<T>();
     pd.push_back(d);
   }
-  launch_pqr<T>(upload(pd), (int)pd.size(), eps_, st);
-  ++launches_;
+  log_shapes("step1", pd);
+  run_pqr(pd);
   const size_t nr = std::max<size_t>(1, who.size());
   int* h = static_cast<int*>(H.stage.alloc((nr + nflags_ + 1) * sizeof(int)));
   SPAQR_HIP(hipMemcpyAsync(h, d_rank, nr * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -973,9 +1028,10 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
   for (size_t i = 0; i < gd.size(); ++i) gd[i].colmap = dpool + gd_map[i];
   for (size_t i = 0; i < sd.size(); ++i) sd[i].colmap = dpool + sd_map[i];
   launch_gather<T>(upload(gd), (int)gd.size(), maxc, st);
-  launch_pqr<T>(upload(pd), (int)pd.size(), eps_, st);
+  log_shapes("step2", pd);
+  run_pqr(pd);
   launch_scatter<T>(upload(sd), (int)sd.size(), st);
-  launches_ += 3;
+  launches_ += 2;
   int* h = static_cast<int*>(H.stage.alloc(std::max<size_t>(1, sel.size()) * sizeof(int)));
   SPAQR_HIP(hipMemcpyAsync(h, d_rank, sel.size() * sizeof(int), hipMemcpyDeviceToHost, st));
   sync();

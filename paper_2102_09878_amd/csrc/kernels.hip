@@ -296,131 +296,6 @@ __global__ __launch_bounds__(BS) void k_qr_update(const QRDesc* __restrict__ D, 
   }
 }
 
-// ---------------------------------------------------------------------------
-// column-pivoted QR (one block per matrix, columns kept in place)
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(BS) void k_pqr(const PQRDesc* __restrict__ D, double eps) {
-  const PQRDesc d = D[blockIdx.x];
-  T* A = static_cast<T*>(d.A);
-  T* V = static_cast<T*>(d.V);
-  T* tau = static_cast<T*>(d.tau);
-  const int64_t lda = d.lda;
-  const int m = d.m, n = d.n;
-  double* vn1 = d.work;
-  double* vn2 = d.work + n;
-  double* done = d.work + 2 * n;
-  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  __shared__ double sh[4];
-  __shared__ double s_bv[4];
-  __shared__ int s_bi[4];
-  const double tol3z = sqrt(DBL_EPSILON);
-
-  double fro = 0.0;
-  for (int j = wv; j < n; j += 4) {
-    const T* y = A + j * lda;
-    double s = 0.0;
-    for (int r = lane; r < m; r += 64) s += (double)y[r] * (double)y[r];
-    s = wave_sum(s);
-    if (lane == 0) {
-      fro += s;
-      s = sqrt(s);
-      vn1[j] = s;
-      vn2[j] = s;
-      done[j] = 0.0;
-    }
-  }
-  // numerical-rank floor: pivots at the rounding level of ||A||_F end the rank
-  const double floor_v = d.noise * sqrt(block_sum(fro, sh));
-  const int kmax = min(m, n);
-  int rank = 0;
-  double r00 = 0.0;
-  for (int i = 0; i < kmax; ++i) {
-    // pivot: largest remaining norm, lowest index on ties
-    double bv = -1.0;
-    int bi = n;
-    for (int j = tid; j < n; j += BS)
-      if (done[j] == 0.0 && (vn1[j] > bv)) bv = vn1[j], bi = j;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ov > bv || (ov == bv && oi < bi)) bv = ov, bi = oi;
-    }
-    __syncthreads();
-    if (lane == 0) s_bv[wv] = bv, s_bi[wv] = bi;
-    __syncthreads();
-    bv = s_bv[0];
-    bi = s_bi[0];
-    for (int w2 = 1; w2 < 4; ++w2)
-      if (s_bv[w2] > bv || (s_bv[w2] == bv && s_bi[w2] < bi)) bv = s_bv[w2], bi = s_bi[w2];
-    const int p = bi;
-    if (p >= n) break;  // no finite remaining norm (NaN input)
-    T* col = A + p * lda;
-    double part = 0.0;
-    for (int r = i + 1 + tid; r < m; r += BS) part += (double)col[r] * (double)col[r];
-    const double xn2 = block_sum(part, sh);
-    const double alpha = col[i];
-    double beta, tv, scal;
-    house_scalars(alpha, xn2, beta, tv, scal);
-    bool stop = fabs(beta) <= floor_v;
-    if (i == 0) r00 = fabs(beta);
-    if (d.forced >= 0)
-      stop = stop || i >= d.forced;
-    else if (i > 0)
-      stop = stop || fabs(beta) < eps * r00;
-    if (stop) break;
-    if (tv != 0.0)
-      for (int r = i + 1 + tid; r < m; r += BS) col[r] = static_cast<T>(col[r] * scal);
-    __syncthreads();
-    if (V) {
-      T* vc = V + (int64_t)i * m;
-      for (int r = tid; r < m; r += BS) vc[r] = r < i ? T(0) : (r == i ? T(1) : col[r]);
-    }
-    if (tid == 0 && tau) tau[i] = static_cast<T>(tv);
-    for (int j = wv; j < n; j += 4) {
-      if (j == p || done[j] != 0.0) continue;
-      T* y = A + j * lda;
-      const double yi = y[i];
-      double dot = 0.0;
-      if (tv != 0.0)
-        for (int r = i + 1 + lane; r < m; r += 64) dot += (double)col[r] * (double)y[r];
-      dot = wave_sum(dot) + yi;
-      const double f = tv * dot;
-      const double nyi = yi - f;
-      if (lane == 0) y[i] = static_cast<T>(nyi);
-      if (tv != 0.0)
-        for (int r = i + 1 + lane; r < m; r += 64) y[r] = static_cast<T>(y[r] - f * (double)col[r]);
-      // norm downdate (LAPACK Working Note 176)
-      const double v1 = vn1[j];
-      if (v1 != 0.0) {
-        const double ay = fabs((double)static_cast<T>(nyi));
-        double temp = 1.0 - (ay / v1) * (ay / v1);
-        temp = temp > 0.0 ? temp : 0.0;
-        const double ratio = v1 / vn2[j];
-        const double temp2 = temp * ratio * ratio;
-        if (temp2 <= tol3z) {
-          double s = 0.0;
-          for (int r = i + 1 + lane; r < m; r += 64) s += (double)y[r] * (double)y[r];
-          s = sqrt(wave_sum(s));
-          if (lane == 0) vn1[j] = s, vn2[j] = s;
-        } else if (lane == 0) {
-          vn1[j] = v1 * sqrt(temp);
-        }
-      }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      col[i] = static_cast<T>(beta);
-      done[p] = 1.0;
-      if (d.piv_out) d.piv_out[i] = p;
-    }
-    for (int r = i + 1 + tid; r < m; r += BS) col[r] = T(0);
-    rank = i + 1;
-    __syncthreads();
-  }
-  if (tid == 0) d.rank_out[0] = rank;
-}
 
 // ---------------------------------------------------------------------------
 // B <- B R^-1 (R upper triangular), rows in parallel
@@ -580,13 +455,6 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, double* tbuf,
 }
 
 template <typename T>
-void launch_pqr(const PQRDesc* d_desc, int n, double eps, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_pqr<T>, dim3(n), dim3(BS), 0, s, d_desc, eps);
-  SPAQR_HIP(hipGetLastError());
-}
-
-template <typename T>
 void launch_trsm(const TrsmDesc* d_desc, int n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_trsm<T>, dim3(n), dim3(BS), 0, s, d_desc);
@@ -627,7 +495,6 @@ void launch_scatter(const ScatterDesc* d_desc, int n, hipStream_t s) {
   template void launch_scatter_csr<T>(T*, const int64_t*, const double*, int64_t, hipStream_t); \
   template void launch_qr<T>(const QRDesc*, const std::vector<QRDesc>&, double*, hipStream_t,   \
                              int*);                                                            \
-  template void launch_pqr<T>(const PQRDesc*, int, double, hipStream_t);                       \
   template void launch_trsm<T>(const TrsmDesc*, int, hipStream_t);                             \
   template void launch_owner<T>(const OwnerDesc*, int, hipStream_t);                           \
   template void launch_rowcopy<T>(const RowCopyDesc*, int, int, hipStream_t);                         \

@@ -172,7 +172,20 @@ struct PQRDesc {
   int* piv_out;      // pivot column per step (min(m,n))
   int64_t lda;
   double noise;
-  int m, n, forced, pad_;
+  int m, n, forced;
+  int blk0, nblk;    // this matrix's column chunks in the launch (set by the launcher)
+  int pad_;
+};
+
+// Per-matrix state of the step-synchronous pivoted QR, double-buffered by
+// step parity (step i reads slot i&1 and writes slot (i+1)&1).
+struct PQRState {
+  double r00, floor, beta;
+  int pivot, pstep, rank, stopped;
+};
+struct PQRPart {
+  double val, fro;
+  int idx, pad_;
 };
 
 // B <- B R^-1 on the columns colmap[0..c) of a group block (nrows x ., ld).
@@ -256,8 +269,20 @@ void launch_scatter_csr(T* base, const int64_t* dst, const double* ahat, int64_t
 template <typename T>
 void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h_desc, double* tbuf, hipStream_t s,
                int* launches);
+// Column-pivoted QR of a batch, one launch per pivot step (columns split in
+// chunks of PQR_CW over work-groups).  The caller provides device scratch:
+// states (2 per matrix), parts (2 per chunk), bmap (one int2 per chunk) and
+// an `active` counter; h_desc must already carry blk0/nblk.
+constexpr int PQR_CW = 64;
 template <typename T>
-void launch_pqr(const PQRDesc* d_desc, int n, double eps, hipStream_t s);
+void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPart* parts,
+                     const int2* bmap, hipStream_t s);
+template <typename T>
+void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRState* states,
+                     PQRPart* parts, const int2* bmap, int* active, int i, double eps, int max_m,
+                     hipStream_t s);
+template <typename T>
+void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int steps, hipStream_t s);
 template <typename T>
 void launch_trsm(const TrsmDesc* d_desc, int n, hipStream_t s);
 template <typename T>
