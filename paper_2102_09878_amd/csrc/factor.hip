@@ -211,8 +211,6 @@ class Factorizer {
   std::set<int> live;
   std::vector<int> pos;
   int level_ = 0, round_ = 0;
-  double* tbuf_ = nullptr;
-  size_t tbuf_cap_ = 0;
   int launches_ = 0, syncs_ = 0;
   double flops_[5] = {0, 0, 0, 0, 0}, bytes_[5] = {0, 0, 0, 0, 0};
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> timers_;
@@ -351,12 +349,17 @@ class Factorizer {
                  what, v.size(), mm, mn, work);
   }
 
-  void ensure_tbuf(size_t n) {
-    if (n > tbuf_cap_) {
-      tbuf_cap_ = std::max<size_t>(n, 2 * tbuf_cap_);
-      tbuf_ = static_cast<double*>(H.arena.alloc(tbuf_cap_ * 32 * 32 * sizeof(double)));
+  // grow-only device scratch (valid for the whole factorization)
+  double* scratch(std::vector<std::pair<double*, size_t>>& pool, int slot, size_t n) {
+    if ((int)pool.size() <= slot) pool.resize(slot + 1, {nullptr, 0});
+    auto& e = pool[slot];
+    if (n > e.second) {
+      e.second = std::max(n, 2 * e.second);
+      e.first = static_cast<double*>(H.arena.alloc(e.second * sizeof(double)));
     }
+    return e.first;
   }
+  std::vector<std::pair<double*, size_t>> qrpool_;
 
   // Batched rank-revealing QR: one launch per pivot step until every
   // matrix has stopped (polled every few steps).
@@ -398,10 +401,19 @@ class Factorizer {
 
   void run_qr(const std::vector<QRDesc>& q) {
     if (q.empty()) return;
-    ensure_tbuf(q.size());
     QRDesc* d = upload(q);
     log_shapes("qr", q);
-    launch_qr<T>(d, q, tbuf_, st, &launches_);
+    QRWork ws{};
+    qr_work_dims(q, &ws.MS, &ws.MT);
+    const size_t nf = q.size();
+    ws.tbuf = scratch(qrpool_, 0, nf * QR_NB * QR_NB);
+    ws.betas = scratch(qrpool_, 1, nf);
+    ws.normp = scratch(qrpool_, 2, nf * ws.MS);
+    ws.dp = scratch(qrpool_, 3, nf * ws.MS * QR_NB);
+    ws.gp = scratch(qrpool_, 4, nf * ws.MS * QR_NB * QR_NB);
+    ws.wp = scratch(qrpool_, 5, nf * ws.MT * ws.MS * QR_NB * QR_TN);
+    ws.w = scratch(qrpool_, 6, nf * ws.MT * QR_NB * QR_TN);
+    launch_qr<T>(d, q, ws, st, &launches_);
   }
 
   int* flags_ = nullptr;

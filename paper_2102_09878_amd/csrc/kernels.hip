@@ -110,194 +110,6 @@ __global__ void k_scatter_csr(T* __restrict__ base, const int64_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// blocked Householder QR
-// ---------------------------------------------------------------------------
-constexpr int QR_NB = 32;
-constexpr int QR_TN = 64;
-
-// Factor columns [j0, j0+kb) of every matrix (rows j0..m-1) and build the
-// triangular factor T of the compact-WY form Q = I - V T V^T.
-template <typename T>
-__global__ __launch_bounds__(BS) void k_qr_panel(const QRDesc* __restrict__ D, int j0,
-                                                 double* __restrict__ tbuf) {
-  const QRDesc d = D[blockIdx.x];
-  const int kk = min(d.m, d.k);
-  if (j0 >= kk) return;
-  const int kb = min(QR_NB, kk - j0);
-  T* A = static_cast<T*>(d.A);
-  T* tau = static_cast<T*>(d.tau);
-  const int64_t lda = d.lda;
-  const int m = d.m;
-  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  __shared__ double sh[4];
-  __shared__ double s_tau[QR_NB];
-  __shared__ double G[QR_NB][QR_NB + 1];
-
-  for (int i = 0; i < kb; ++i) {
-    const int c = j0 + i;
-    T* col = A + c * lda;
-    double part = 0.0;
-    for (int r = c + 1 + tid; r < m; r += BS) {
-      const double v = col[r];
-      part += v * v;
-    }
-    const double xn2 = block_sum(part, sh);
-    const double alpha = col[c];
-    double beta, tv, scal;
-    house_scalars(alpha, xn2, beta, tv, scal);
-    if (tv != 0.0)
-      for (int r = c + 1 + tid; r < m; r += BS) col[r] = static_cast<T>(col[r] * scal);
-    __syncthreads();
-    if (tv != 0.0) {
-      for (int cc = c + 1 + wv; cc < j0 + kb; cc += 4) {
-        T* y = A + cc * lda;
-        const double yc = y[c];
-        double dot = 0.0;
-        for (int r = c + 1 + lane; r < m; r += 64) dot += (double)col[r] * (double)y[r];
-        dot = wave_sum(dot) + yc;
-        const double f = tv * dot;
-        if (lane == 0) y[c] = static_cast<T>(yc - f);
-        for (int r = c + 1 + lane; r < m; r += 64) y[r] = static_cast<T>(y[r] - f * (double)col[r]);
-      }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      col[c] = static_cast<T>(beta);
-      tau[c] = static_cast<T>(tv);
-      s_tau[i] = static_cast<double>(static_cast<T>(tv));
-    }
-    __syncthreads();
-  }
-  // G[a][b] = v_a^T v_b for a < b (v_a has a unit entry at row j0+a)
-  for (int pr = wv; pr < kb * kb; pr += 4) {
-    const int a = pr / kb, b = pr % kb;
-    if (a >= b) continue;
-    const T* va = A + (j0 + a) * lda;
-    const T* vb = A + (j0 + b) * lda;
-    double dot = 0.0;
-    for (int r = j0 + b + 1 + lane; r < m; r += 64) dot += (double)va[r] * (double)vb[r];
-    dot = wave_sum(dot);
-    if (lane == 0) G[a][b] = dot + (double)va[j0 + b];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double* Tm = tbuf + (int64_t)blockIdx.x * QR_NB * QR_NB;
-    for (int i = 0; i < kb; ++i) {
-      Tm[i * QR_NB + i] = s_tau[i];
-      for (int a = 0; a < i; ++a) {
-        double acc = 0.0;
-        for (int b = a; b < i; ++b) acc += Tm[a * QR_NB + b] * G[b][i];
-        Tm[a * QR_NB + i] = -s_tau[i] * acc;
-      }
-      for (int a = i + 1; a < QR_NB; ++a) Tm[a * QR_NB + i] = 0.0;
-    }
-  }
-}
-
-// C <- (I - V T V^T)^T C on a tile of QR_TN trailing columns.
-template <typename T>
-__global__ __launch_bounds__(BS) void k_qr_update(const QRDesc* __restrict__ D, int j0,
-                                                  const double* __restrict__ tbuf) {
-  const QRDesc d = D[blockIdx.x];
-  const int kk = min(d.m, d.k);
-  if (j0 >= kk) return;
-  const int kb = min(QR_NB, kk - j0);
-  const int c0 = j0 + kb + blockIdx.y * QR_TN;
-  if (c0 >= d.n) return;
-  const int nc = min(QR_TN, d.n - c0);
-  T* A = static_cast<T*>(d.A);
-  const int64_t lda = d.lda;
-  const int m = d.m;
-  const int tid = threadIdx.x;
-  __shared__ double W[QR_NB][QR_TN + 1];
-  __shared__ T Vs[32][QR_NB + 1];
-  __shared__ T Cs[32][QR_TN + 1];
-  const double* Tm = tbuf + (int64_t)blockIdx.x * QR_NB * QR_NB;
-
-  // phase 1: W = V^T C   (thread -> a = tid>>3, columns cg*8 .. cg*8+7)
-  const int pa = tid >> 3, pcg = tid & 7;
-  double acc[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) acc[j] = 0.0;
-  for (int r0 = j0; r0 < m; r0 += 32) {
-    for (int e = tid; e < 32 * QR_NB; e += BS) {
-      const int rr = e & 31, a = e >> 5;
-      const int r = r0 + rr;
-      T v = T(0);
-      if (a < kb && r < m) {
-        if (r == j0 + a)
-          v = T(1);
-        else if (r > j0 + a)
-          v = A[r + (j0 + a) * lda];
-      }
-      Vs[rr][a] = v;
-    }
-    for (int e = tid; e < 32 * QR_TN; e += BS) {
-      const int rr = e & 31, cc = e >> 5;
-      const int r = r0 + rr;
-      Cs[rr][cc] = (r < m && cc < nc) ? A[r + (c0 + cc) * lda] : T(0);
-    }
-    __syncthreads();
-    if (pa < kb) {
-      const int rmax = min(32, m - r0);
-      for (int rr = 0; rr < rmax; ++rr) {
-        const double v = Vs[rr][pa];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) acc[j] += v * (double)Cs[rr][pcg * 8 + j];
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int j = 0; j < 8; ++j) W[pa][pcg * 8 + j] = acc[j];
-  __syncthreads();
-  // phase 2: W <- T^T W
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    double s = 0.0;
-    if (pa < kb)
-      for (int a = 0; a <= pa; ++a) s += Tm[a * QR_NB + pa] * W[a][pcg * 8 + j];
-    acc[j] = s;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < 8; ++j) W[pa][pcg * 8 + j] = acc[j];
-  __syncthreads();
-  // phase 3: C -= V W   (thread -> row rr = tid & 31, columns cg*8..)
-  const int rr = tid & 31, cg = tid >> 5;
-  for (int r0 = j0; r0 < m; r0 += 32) {
-    for (int e = tid; e < 32 * QR_NB; e += BS) {
-      const int r2 = e & 31, a = e >> 5;
-      const int r = r0 + r2;
-      T v = T(0);
-      if (a < kb && r < m) {
-        if (r == j0 + a)
-          v = T(1);
-        else if (r > j0 + a)
-          v = A[r + (j0 + a) * lda];
-      }
-      Vs[r2][a] = v;
-    }
-    __syncthreads();
-    const int r = r0 + rr;
-    if (r < m) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int cc = cg * 8 + j;
-        if (cc < nc) {
-          double s = 0.0;
-          for (int a = 0; a < kb; ++a) s += (double)Vs[rr][a] * W[a][cc];
-          T* p = A + r + (c0 + cc) * lda;
-          *p = static_cast<T>(*p - s);
-        }
-      }
-    }
-    __syncthreads();
-  }
-}
-
-
-// ---------------------------------------------------------------------------
 // B <- B R^-1 (R upper triangular), rows in parallel
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -428,33 +240,6 @@ void launch_scatter_csr(T* base, const int64_t* dst, const double* ahat, int64_t
 }
 
 template <typename T>
-void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, double* tbuf, hipStream_t s,
-               int* launches) {
-  if (h.empty()) return;
-  int kmax = 0;
-  for (auto& d : h) kmax = std::max(kmax, std::min(d.m, d.k));
-  for (int j0 = 0; j0 < kmax; j0 += QR_NB) {
-    int tiles = 0;
-    for (auto& d : h) {
-      const int kk = std::min(d.m, d.k);
-      if (j0 >= kk) continue;
-      const int kb = std::min(QR_NB, kk - j0);
-      const int rest = d.n - j0 - kb;
-      if (rest > 0) tiles = std::max(tiles, (rest + QR_TN - 1) / QR_TN);
-    }
-    hipLaunchKernelGGL(k_qr_panel<T>, dim3((unsigned)h.size()), dim3(BS), 0, s, d_desc, j0, tbuf);
-    SPAQR_HIP(hipGetLastError());
-    ++*launches;
-    if (tiles > 0) {
-      hipLaunchKernelGGL(k_qr_update<T>, dim3((unsigned)h.size(), tiles), dim3(BS), 0, s, d_desc, j0,
-                         (const double*)tbuf);
-      SPAQR_HIP(hipGetLastError());
-      ++*launches;
-    }
-  }
-}
-
-template <typename T>
 void launch_trsm(const TrsmDesc* d_desc, int n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_trsm<T>, dim3(n), dim3(BS), 0, s, d_desc);
@@ -493,8 +278,6 @@ void launch_scatter(const ScatterDesc* d_desc, int n, hipStream_t s) {
 #define SPAQR_INST(T)                                                                          \
   template void launch_gather<T>(const GatherDesc*, int, int, hipStream_t);                    \
   template void launch_scatter_csr<T>(T*, const int64_t*, const double*, int64_t, hipStream_t); \
-  template void launch_qr<T>(const QRDesc*, const std::vector<QRDesc>&, double*, hipStream_t,   \
-                             int*);                                                            \
   template void launch_trsm<T>(const TrsmDesc*, int, hipStream_t);                             \
   template void launch_owner<T>(const OwnerDesc*, int, hipStream_t);                           \
   template void launch_rowcopy<T>(const RowCopyDesc*, int, int, hipStream_t);                         \

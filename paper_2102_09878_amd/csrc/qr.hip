@@ -1,0 +1,504 @@
+// Batched blocked Householder QR for gfx950 (wave64): the block Householder
+// eliminations of Section 2.3 and the interface scalings of Section 2.4.
+//
+// Reflectors follow the LAPACK convention (beta = -sign(alpha)||x||,
+// sign(0) = +1, tau = 0 for a zero tail) and are applied left to right, so
+// every front sees exactly the reflector sequence of an unblocked
+// column-by-column Householder QR; blocking only regroups the updates.
+//
+// Panel (QR_NB columns):
+//  * one work-group per front when fronts are short (the leaf level: many
+//    fronts of ~1000 rows in one launch);
+//  * row-split over QR_RS-row segments when a front is tall (fronts of
+//    10^4 rows that are eliminated alone): per column, one launch applies
+//    the previous reflector to the segment and forms norm partials, one
+//    launch forms the reflector and the dot partials for the remaining
+//    panel columns.  Partials are reduced in a fixed order (deterministic).
+// Trailing update C <- (I - V T V^T)^T C over (front, 64-column tile, row
+// segment) blocks: W_s = V_s^T C_s per segment, W = T^T sum_s W_s, then
+// C_s -= V_s W.
+#include <hip/hip_runtime.h>
+
+#include "spaqr_impl.h"
+
+namespace spaqr {
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int NB = QR_NB;
+constexpr int TN = QR_TN;
+constexpr int RS = QR_RS;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__device__ __forceinline__ void house_scalars(double alpha, double xn2, double& beta, double& tau,
+                                              double& scal) {
+  if (xn2 == 0.0) {
+    beta = alpha;
+    tau = 0.0;
+    scal = 1.0;
+  } else {
+    const double s = alpha < 0.0 ? -1.0 : 1.0;
+    beta = -s * sqrt(alpha * alpha + xn2);
+    tau = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+}
+
+// T of the compact-WY form from tau and the strictly-upper Gram G[a][b] = v_a^T v_b
+__device__ void build_t(double* Tm, const double* s_tau, const double (*G)[NB + 1], int kb) {
+  for (int i = 0; i < kb; ++i) {
+    Tm[i * NB + i] = s_tau[i];
+    for (int a = 0; a < i; ++a) {
+      double acc = 0.0;
+      for (int b = a; b < i; ++b) acc += Tm[a * NB + b] * G[b][i];
+      Tm[a * NB + i] = -s_tau[i] * acc;
+    }
+    for (int a = i + 1; a < NB; ++a) Tm[a * NB + i] = 0.0;
+  }
+}
+
+__device__ __forceinline__ int seg_lo(int j0) { return j0 / RS; }
+__device__ __forceinline__ int seg_hi(int m) { return (m + RS - 1) / RS; }
+
+// ---------------------------------------------------------------------------
+// panel, one work-group per front
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BS) void k_qr_panel(const QRDesc* __restrict__ D, int j0,
+                                                 double* __restrict__ tbuf) {
+  const QRDesc d = D[blockIdx.x];
+  const int kk = min(d.m, d.k);
+  if (j0 >= kk) return;
+  const int kb = min(NB, kk - j0);
+  T* A = static_cast<T*>(d.A);
+  T* tau = static_cast<T*>(d.tau);
+  const int64_t lda = d.lda;
+  const int m = d.m;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  __shared__ double sh[4];
+  __shared__ double s_tau[NB];
+  __shared__ double G[NB][NB + 1];
+
+  for (int i = 0; i < kb; ++i) {
+    const int c = j0 + i;
+    T* col = A + c * lda;
+    double part = 0.0;
+    for (int r = c + 1 + tid; r < m; r += BS) {
+      const double v = col[r];
+      part += v * v;
+    }
+    const double xn2 = block_sum(part, sh);
+    const double alpha = col[c];
+    double beta, tv, scal;
+    house_scalars(alpha, xn2, beta, tv, scal);
+    if (tv != 0.0)
+      for (int r = c + 1 + tid; r < m; r += BS) col[r] = static_cast<T>(col[r] * scal);
+    __syncthreads();
+    if (tv != 0.0) {
+      for (int cc = c + 1 + wv; cc < j0 + kb; cc += 4) {
+        T* y = A + cc * lda;
+        const double yc = y[c];
+        double dot = 0.0;
+        for (int r = c + 1 + lane; r < m; r += 64) dot += (double)col[r] * (double)y[r];
+        dot = wave_sum(dot) + yc;
+        const double f = tv * dot;
+        if (lane == 0) y[c] = static_cast<T>(yc - f);
+        for (int r = c + 1 + lane; r < m; r += 64) y[r] = static_cast<T>(y[r] - f * (double)col[r]);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      col[c] = static_cast<T>(beta);
+      tau[c] = static_cast<T>(tv);
+      s_tau[i] = static_cast<double>(static_cast<T>(tv));
+    }
+    __syncthreads();
+  }
+  for (int pr = wv; pr < kb * kb; pr += 4) {
+    const int a = pr / kb, b = pr % kb;
+    if (a >= b) continue;
+    const T* va = A + (j0 + a) * lda;
+    const T* vb = A + (j0 + b) * lda;
+    double dot = 0.0;
+    for (int r = j0 + b + 1 + lane; r < m; r += 64) dot += (double)va[r] * (double)vb[r];
+    dot = wave_sum(dot);
+    if (lane == 0) G[a][b] = dot + (double)va[j0 + b];
+  }
+  __syncthreads();
+  if (tid == 0) build_t(tbuf + (int64_t)blockIdx.x * NB * NB, s_tau, G, kb);
+}
+
+// ---------------------------------------------------------------------------
+// panel, row-split (tall fronts)
+// ---------------------------------------------------------------------------
+
+// Step a(i): apply reflector i-1 to the segment's rows of panel columns
+// j0+i .. j0+kb-1 (dots reduced from step b(i-1)), finalise column j0+i-1,
+// then publish the segment's partial ||A[j0+i+1:, j0+i]||^2.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_qrp_a(const QRDesc* __restrict__ D, int j0, int i, QRWork ws) {
+  const QRDesc d = D[blockIdx.x];
+  const int kk = min(d.m, d.k);
+  if (j0 >= kk) return;
+  const int kb = min(NB, kk - j0);
+  if (i > kb) return;
+  const int f = blockIdx.x, s = blockIdx.y;
+  const int m = d.m;
+  const int r0 = max(j0, s * RS), r1 = min(m, (s + 1) * RS);
+  if (r0 >= r1) return;
+  T* A = static_cast<T*>(d.A);
+  const int64_t lda = d.lda;
+  const int tid = threadIdx.x;
+  const int c = j0 + i;
+  __shared__ double sh[4];
+  __shared__ double w[NB];
+  if (i > 0) {
+    const int pc = c - 1;
+    const int ncol = j0 + kb - c;
+    if (tid < ncol) {
+      double acc = 0.0;
+      for (int sg = seg_lo(j0); sg < seg_hi(m); ++sg) acc += ws.dp[((int64_t)f * ws.MS + sg) * NB + (c - j0) + tid];
+      w[tid] = acc;
+    }
+    __syncthreads();
+    const double tp = (double)static_cast<const T*>(d.tau)[pc];
+    if (tp != 0.0) {
+      const T* vcol = A + (int64_t)pc * lda;
+      for (int r = max(r0, pc) + tid; r < r1; r += BS) {
+        const double v = r == pc ? 1.0 : (double)vcol[r];
+        for (int j = 0; j < ncol; ++j) {
+          T* y = A + (int64_t)(c + j) * lda + r;
+          *y = static_cast<T>((double)*y - tp * w[j] * v);
+        }
+      }
+    }
+    if (tid == 0 && pc >= r0 && pc < r1) A[pc + (int64_t)pc * lda] = static_cast<T>(ws.betas[f]);
+  }
+  if (i < kb) {
+    // same thread-to-row mapping as the update above: no barrier needed
+    const T* col = A + (int64_t)c * lda;
+    double part = 0.0;
+    const int rstart = max(r0, c + 1);
+    for (int r = max(r0, c - 1) + tid; r < r1; r += BS)
+      if (r >= rstart) {
+        const double v = col[r];
+        part += v * v;
+      }
+    part = block_sum(part, sh);
+    if (tid == 0) ws.normp[(int64_t)f * ws.MS + s] = part;
+  }
+}
+
+// Step b(i): reflector of column j0+i (every segment computes the same
+// scalars), scale the segment's part of it, publish dot partials.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_qrp_b(const QRDesc* __restrict__ D, int j0, int i, QRWork ws) {
+  const QRDesc d = D[blockIdx.x];
+  const int kk = min(d.m, d.k);
+  if (j0 >= kk) return;
+  const int kb = min(NB, kk - j0);
+  if (i >= kb) return;
+  const int f = blockIdx.x, s = blockIdx.y;
+  const int m = d.m;
+  const int r0 = max(j0, s * RS), r1 = min(m, (s + 1) * RS);
+  if (r0 >= r1) return;
+  T* A = static_cast<T*>(d.A);
+  const int64_t lda = d.lda;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int c = j0 + i;
+  double xn2 = 0.0;
+  for (int sg = seg_lo(j0); sg < seg_hi(m); ++sg) xn2 += ws.normp[(int64_t)f * ws.MS + sg];
+  T* col = A + (int64_t)c * lda;
+  const double alpha = col[c];
+  double beta, tv, scal;
+  house_scalars(alpha, xn2, beta, tv, scal);
+  const int rs = max(r0, c + 1);
+  if (tv != 0.0)
+    for (int r = rs + tid; r < r1; r += BS) col[r] = static_cast<T>(col[r] * scal);
+  __syncthreads();
+  const bool has_c = c >= r0 && c < r1;
+  for (int cc = c + 1 + wv; cc < j0 + kb; cc += 4) {
+    const T* y = A + (int64_t)cc * lda;
+    double dot = 0.0;
+    for (int r = rs + lane; r < r1; r += 64) dot += (double)col[r] * (double)y[r];
+    dot = wave_sum(dot);
+    if (lane == 0) ws.dp[((int64_t)f * ws.MS + s) * NB + (cc - j0)] = dot + (has_c ? (double)y[c] : 0.0);
+  }
+  if (has_c && tid == 0) {
+    static_cast<T*>(d.tau)[c] = static_cast<T>(tv);
+    ws.betas[f] = beta;
+  }
+}
+
+// Gram partials of the panel's reflectors over the segment.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_qrp_gram(const QRDesc* __restrict__ D, int j0, QRWork ws) {
+  const QRDesc d = D[blockIdx.x];
+  const int kk = min(d.m, d.k);
+  if (j0 >= kk) return;
+  const int kb = min(NB, kk - j0);
+  const int f = blockIdx.x, s = blockIdx.y;
+  const int m = d.m;
+  const int r0 = max(j0, s * RS), r1 = min(m, (s + 1) * RS);
+  if (r0 >= r1) return;
+  const T* A = static_cast<const T*>(d.A);
+  const int64_t lda = d.lda;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  double* gp = ws.gp + ((int64_t)f * ws.MS + s) * NB * NB;
+  for (int pr = wv; pr < kb * kb; pr += 4) {
+    const int a = pr / kb, b = pr % kb;
+    if (a >= b) continue;
+    const T* va = A + (int64_t)(j0 + a) * lda;
+    const T* vb = A + (int64_t)(j0 + b) * lda;
+    double dot = 0.0;
+    for (int r = max(r0, j0 + b + 1) + lane; r < r1; r += 64) dot += (double)va[r] * (double)vb[r];
+    dot = wave_sum(dot);
+    if (lane == 0) {
+      const int rb = j0 + b;
+      gp[a * NB + b] = dot + ((rb >= r0 && rb < r1) ? (double)va[rb] : 0.0);
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_qrp_tmat(const QRDesc* __restrict__ D, int j0, QRWork ws) {
+  const QRDesc d = D[blockIdx.x];
+  const int kk = min(d.m, d.k);
+  if (j0 >= kk) return;
+  const int kb = min(NB, kk - j0);
+  const int f = blockIdx.x;
+  __shared__ double G[NB][NB + 1];
+  __shared__ double s_tau[NB];
+  for (int e = threadIdx.x; e < NB * NB; e += BS) {
+    const int a = e / NB, b = e % NB;
+    double acc = 0.0;
+    if (a < b && b < kb)
+      for (int sg = seg_lo(j0); sg < seg_hi(d.m); ++sg) acc += ws.gp[((int64_t)f * ws.MS + sg) * NB * NB + e];
+    G[a][b] = acc;
+  }
+  if (threadIdx.x < kb) s_tau[threadIdx.x] = (double)static_cast<const T*>(d.tau)[j0 + threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x == 0) build_t(ws.tbuf + (int64_t)f * NB * NB, s_tau, G, kb);
+}
+
+// ---------------------------------------------------------------------------
+// trailing update
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T vref(const T* A, int64_t lda, int j0, int a, int kb, int r) {
+  if (a >= kb) return T(0);
+  const int ra = j0 + a;
+  if (r == ra) return T(1);
+  if (r > ra) return A[r + (int64_t)ra * lda];
+  return T(0);
+}
+
+// W_s = V_s^T C_s for one (front, tile, segment)
+template <typename T>
+__global__ __launch_bounds__(BS) void k_qru_w(const QRDesc* __restrict__ D, int j0, QRWork ws) {
+  const QRDesc d = D[blockIdx.x];
+  const int kk = min(d.m, d.k);
+  if (j0 >= kk) return;
+  const int kb = min(NB, kk - j0);
+  const int t = blockIdx.y, s = blockIdx.z;
+  const int c0 = j0 + kb + t * TN;
+  if (c0 >= d.n) return;
+  const int m = d.m;
+  const int r0 = max(j0, s * RS), r1 = min(m, (s + 1) * RS);
+  if (r0 >= r1) return;
+  const int nc = min(TN, d.n - c0);
+  const T* A = static_cast<const T*>(d.A);
+  const int64_t lda = d.lda;
+  const int tid = threadIdx.x;
+  __shared__ T Vs[32][NB + 1];
+  __shared__ T Cs[32][TN + 1];
+  const int pa = tid >> 3, pcg = tid & 7;
+  double acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+  for (int rb = r0; rb < r1; rb += 32) {
+    for (int e = tid; e < 32 * NB; e += BS) {
+      const int rr = e & 31, a = e >> 5;
+      const int r = rb + rr;
+      Vs[rr][a] = r < r1 ? vref(A, lda, j0, a, kb, r) : T(0);
+    }
+    for (int e = tid; e < 32 * TN; e += BS) {
+      const int rr = e & 31, cc = e >> 5;
+      const int r = rb + rr;
+      Cs[rr][cc] = (r < r1 && cc < nc) ? A[r + (int64_t)(c0 + cc) * lda] : T(0);
+    }
+    __syncthreads();
+    if (pa < kb) {
+      const int rmax = min(32, r1 - rb);
+      for (int rr = 0; rr < rmax; ++rr) {
+        const double v = Vs[rr][pa];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] += v * (double)Cs[rr][pcg * 8 + j];
+      }
+    }
+    __syncthreads();
+  }
+  double* out = ws.wp + (((int64_t)blockIdx.x * ws.MT + t) * ws.MS + s) * NB * TN;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) out[pa * TN + pcg * 8 + j] = acc[j];
+}
+
+// W = T^T sum_s W_s for one (front, tile)
+template <typename T>
+__global__ __launch_bounds__(BS) void k_qru_reduce(const QRDesc* __restrict__ D, int j0, QRWork ws) {
+  const QRDesc d = D[blockIdx.x];
+  const int kk = min(d.m, d.k);
+  if (j0 >= kk) return;
+  const int kb = min(NB, kk - j0);
+  const int t = blockIdx.y;
+  const int c0 = j0 + kb + t * TN;
+  if (c0 >= d.n) return;
+  __shared__ double W[NB][TN + 1];
+  const int tid = threadIdx.x;
+  const int64_t base = ((int64_t)blockIdx.x * ws.MT + t) * ws.MS;
+  for (int e = tid; e < NB * TN; e += BS) {
+    double acc = 0.0;
+    for (int sg = seg_lo(j0); sg < seg_hi(d.m); ++sg) acc += ws.wp[(base + sg) * NB * TN + e];
+    W[e / TN][e % TN] = acc;
+  }
+  __syncthreads();
+  const double* Tm = ws.tbuf + (int64_t)blockIdx.x * NB * NB;
+  double* out = ws.w + ((int64_t)blockIdx.x * ws.MT + t) * NB * TN;
+  for (int e = tid; e < NB * TN; e += BS) {
+    const int i = e / TN, cc = e % TN;
+    double s = 0.0;
+    if (i < kb)
+      for (int a = 0; a <= i; ++a) s += Tm[a * NB + i] * W[a][cc];
+    out[e] = s;
+  }
+}
+
+// C_s -= V_s W for one (front, tile, segment)
+template <typename T>
+__global__ __launch_bounds__(BS) void k_qru_apply(const QRDesc* __restrict__ D, int j0, QRWork ws) {
+  const QRDesc d = D[blockIdx.x];
+  const int kk = min(d.m, d.k);
+  if (j0 >= kk) return;
+  const int kb = min(NB, kk - j0);
+  const int t = blockIdx.y, s = blockIdx.z;
+  const int c0 = j0 + kb + t * TN;
+  if (c0 >= d.n) return;
+  const int m = d.m;
+  const int r0 = max(j0, s * RS), r1 = min(m, (s + 1) * RS);
+  if (r0 >= r1) return;
+  const int nc = min(TN, d.n - c0);
+  T* A = static_cast<T*>(d.A);
+  const int64_t lda = d.lda;
+  const int tid = threadIdx.x;
+  __shared__ double W[NB][TN + 1];
+  __shared__ T Vs[32][NB + 1];
+  const double* win = ws.w + ((int64_t)blockIdx.x * ws.MT + t) * NB * TN;
+  for (int e = tid; e < NB * TN; e += BS) W[e / TN][e % TN] = win[e];
+  const int rr = tid & 31, cg = tid >> 5;
+  for (int rb = r0; rb < r1; rb += 32) {
+    __syncthreads();
+    for (int e = tid; e < 32 * NB; e += BS) {
+      const int r2 = e & 31, a = e >> 5;
+      const int r = rb + r2;
+      Vs[r2][a] = r < r1 ? vref(A, lda, j0, a, kb, r) : T(0);
+    }
+    __syncthreads();
+    const int r = rb + rr;
+    if (r < r1) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int cc = cg * 8 + j;
+        if (cc < nc) {
+          double sum = 0.0;
+          for (int a = 0; a < kb; ++a) sum += (double)Vs[rr][a] * W[a][cc];
+          T* p = A + r + (int64_t)(c0 + cc) * lda;
+          *p = static_cast<T>((double)*p - sum);
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void qr_work_dims(const std::vector<QRDesc>& h, int* MS, int* MT) {
+  int ms = 1, mt = 1;
+  for (auto& d : h) {
+    ms = std::max(ms, (d.m + RS - 1) / RS);
+    const int kk = std::min(d.m, d.k);
+    if (kk > 0) mt = std::max(mt, (d.n - std::min(NB, kk) + TN - 1) / TN);
+  }
+  *MS = ms;
+  *MT = std::max(1, mt);
+}
+
+template <typename T>
+void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork& ws, hipStream_t s,
+               int* launches) {
+  if (h.empty()) return;
+  const unsigned nf = (unsigned)h.size();
+  int kmax = 0, mmax = 0;
+  for (auto& d : h) {
+    kmax = std::max(kmax, std::min(d.m, d.k));
+    mmax = std::max(mmax, d.m);
+  }
+  // tall fronts: row-split panels
+  const bool split = mmax > 2 * RS;
+  for (int j0 = 0; j0 < kmax; j0 += NB) {
+    int tiles = 0, segs = 1, kbmax = 0;
+    for (auto& d : h) {
+      const int kk = std::min(d.m, d.k);
+      if (j0 >= kk) continue;
+      const int kb = std::min(NB, kk - j0);
+      kbmax = std::max(kbmax, kb);
+      const int rest = d.n - j0 - kb;
+      if (rest > 0) tiles = std::max(tiles, (rest + TN - 1) / TN);
+      segs = std::max(segs, (d.m + RS - 1) / RS);
+    }
+    if (split) {
+      const dim3 g(nf, segs);
+      for (int i = 0; i <= kbmax; ++i) {
+        hipLaunchKernelGGL(k_qrp_a<T>, g, dim3(BS), 0, s, d_desc, j0, i, ws);
+        ++*launches;
+        if (i < kbmax) {
+          hipLaunchKernelGGL(k_qrp_b<T>, g, dim3(BS), 0, s, d_desc, j0, i, ws);
+          ++*launches;
+        }
+      }
+      hipLaunchKernelGGL(k_qrp_gram<T>, g, dim3(BS), 0, s, d_desc, j0, ws);
+      hipLaunchKernelGGL(k_qrp_tmat<T>, dim3(nf), dim3(BS), 0, s, d_desc, j0, ws);
+      *launches += 2;
+    } else {
+      hipLaunchKernelGGL(k_qr_panel<T>, dim3(nf), dim3(BS), 0, s, d_desc, j0, ws.tbuf);
+      ++*launches;
+    }
+    SPAQR_HIP(hipGetLastError());
+    if (tiles > 0) {
+      const dim3 g3(nf, tiles, segs), g2(nf, tiles);
+      hipLaunchKernelGGL(k_qru_w<T>, g3, dim3(BS), 0, s, d_desc, j0, ws);
+      hipLaunchKernelGGL(k_qru_reduce<T>, g2, dim3(BS), 0, s, d_desc, j0, ws);
+      hipLaunchKernelGGL(k_qru_apply<T>, g3, dim3(BS), 0, s, d_desc, j0, ws);
+      SPAQR_HIP(hipGetLastError());
+      *launches += 3;
+    }
+  }
+}
+
+template void launch_qr<double>(const QRDesc*, const std::vector<QRDesc>&, const QRWork&, hipStream_t, int*);
+template void launch_qr<float>(const QRDesc*, const std::vector<QRDesc>&, const QRWork&, hipStream_t, int*);
+
+}  // namespace spaqr

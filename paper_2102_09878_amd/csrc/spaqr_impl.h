@@ -266,8 +266,26 @@ template <typename T>
 void launch_gather(const GatherDesc* d_desc, int n, int max_cols, hipStream_t s);
 template <typename T>
 void launch_scatter_csr(T* base, const int64_t* dst, const double* ahat, int64_t nnz, hipStream_t s);
+// Blocked Householder QR of a batch.  Panels of QR_NB columns; a tall panel
+// is split over row segments of QR_RS rows (two launches per column), the
+// trailing update over (front, column tile, row segment) blocks with a
+// deterministic two-stage reduction of V^T C.
+constexpr int QR_NB = 32;
+constexpr int QR_TN = 64;
+constexpr int QR_RS = 1024;
+struct QRWork {
+  double* tbuf;   // nfront * NB * NB        compact-WY T factors
+  double* betas;  // nfront                  last diagonal of a row-split panel
+  double* normp;  // nfront * MS             norm partials
+  double* dp;     // nfront * MS * NB        dot partials
+  double* gp;     // nfront * MS * NB * NB   Gram partials
+  double* wp;     // nfront * MT * MS * NB * TN  partial V^T C
+  double* w;      // nfront * MT * NB * TN        reduced T^T V^T C
+  int MS, MT;     // max row segments, max column tiles
+};
+void qr_work_dims(const std::vector<QRDesc>& h, int* MS, int* MT);
 template <typename T>
-void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h_desc, double* tbuf, hipStream_t s,
+void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h_desc, const QRWork& ws, hipStream_t s,
                int* launches);
 // Column-pivoted QR of a batch, one launch per pivot step (columns split in
 // chunks of PQR_CW over work-groups).  The caller provides device scratch:
