@@ -86,6 +86,12 @@ typedef struct {
   double bytes[5];           /* scale, sparsify, merge; and bytes moved per phase   */
   double phase_seconds[5];   /* wall time per phase of the last factorization       */
   double factor_seconds;     /* wall time of the last factorization                 */
+  /* Per-launch timing of one kernel family, chosen by spaqr_time_kernel();
+   * accumulated over every factorization and solve since that call. */
+  int64_t kernel_calls;      /* launches timed                                      */
+  double kernel_seconds;     /* sum of their HIP-event durations                    */
+  double kernel_bytes;       /* algorithmic bytes those launches move               */
+  double kernel_flops;       /* algorithmic flops of those launches                 */
 } spaqr_stats;
 
 typedef struct {
@@ -147,6 +153,15 @@ int spaqr_cgls(spaqr_handle h, const double* b_dev, double tol, int32_t max_iter
 /* Statistics of the last factorization (Section 4.2 quantities, the
  * per-phase ledger, launch and synchronisation counts). */
 int spaqr_factor_stats(spaqr_handle h, spaqr_stats* out);
+
+/* Time every `every`-th launch (every >= 1) of one kernel family with HIP
+ * events on the handle's stream and count the algorithmic bytes and flops
+ * of the timed launches (exposed through spaqr_factor_stats); resets the
+ * counters.  family: "pqr_step" (one pivot step of the batched
+ * rank-revealing QRs) or "apply" (one batch of W^-1 / W^-T ops), or
+ * NULL / "" to stop.  SPAQR_EARG for an unknown family or every < 1.
+ * Measurement aid: each timed launch adds two event records. */
+int spaqr_time_kernel(spaqr_handle h, const char* family, int32_t every);
 
 /* Rank decisions of the last factorization, in decision order (host
  * buffer of capacity cap); *n receives the count. */

@@ -6,4 +6,4 @@ include/spaqr.h); ``spaqr`` is its thin Python binding.
 from .spaqr import (Solver, SpaqrError, load, spaqr_analyze, spaqr_apply, spaqr_apply_op,  # noqa: F401
                     spaqr_cgls, spaqr_destroy, spaqr_factor_stats, spaqr_factorize,
                     spaqr_factorize_forced, spaqr_get_op, spaqr_get_ordering, spaqr_get_ranks,
-                    spaqr_set_values)
+                    spaqr_set_values, spaqr_time_kernel)

@@ -124,6 +124,7 @@ int spaqr_apply_op(spaqr_handle h, int32_t op, const double* in_dev, double* out
       SPAQR_HIP(hipMemcpyAsync(out_dev, in_dev, H.P.N * sizeof(double), hipMemcpyDeviceToDevice, H.stream));
     spaqr::apply_op(H, op == SPAQR_WINVT, out_dev);
     SPAQR_HIP(hipStreamSynchronize(H.stream));
+    H.kt.harvest();
     return SPAQR_OK;
   });
 }
@@ -141,6 +142,22 @@ int spaqr_factor_stats(spaqr_handle h, spaqr_stats* out) {
     if (!h || !out) throw spaqr::Error(SPAQR_EARG, "null argument");
     if (!h->h.factored) throw spaqr::Error(SPAQR_ESTATE, "factorize first");
     *out = h->h.stats;
+    out->kernel_calls = h->h.kt.calls;
+    out->kernel_seconds = h->h.kt.seconds;
+    out->kernel_bytes = h->h.kt.bytes;
+    out->kernel_flops = h->h.kt.flops;
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_time_kernel(spaqr_handle h, const char* family, int32_t every) {
+  return guard(h, [&]() -> int {
+    if (!h) throw spaqr::Error(SPAQR_EARG, "null handle");
+    const std::string f = family ? family : "";
+    if (!f.empty() && f != "pqr_step" && f != "apply")
+      throw spaqr::Error(SPAQR_EARG, "unknown kernel family '" + f + "'");
+    if (every < 1) throw spaqr::Error(SPAQR_EARG, "every must be >= 1");
+    h->h.kt.reset(f.c_str(), every);
     return SPAQR_OK;
   });
 }

@@ -361,6 +361,26 @@ class Factorizer {
   }
   std::vector<std::pair<double*, size_t>> qrpool_;
 
+  // Algorithmic traffic of a timed rank-revealing-QR batch, once its ranks
+  // are known: at step i a live matrix reads and writes its (m-i) x (n-i-1)
+  // trailing block and reads its pivot column.
+  void account_pqr(const std::vector<PQRDesc>& q, const int* ranks) {
+    if (!H.kt.on("pqr_step")) return;
+    for (int i : timed_steps_)
+      for (size_t k = 0; k < q.size(); ++k) {
+        const double m = q[k].m, n = q[k].n;
+        const int r = ranks[k];
+        if (i < r) {
+          H.kt.bytes += sizeof(T) * ((m - i) * (n - i - 1) * 2.0 + (m - i));
+          H.kt.flops += 4.0 * (m - i) * (n - i - 1);
+        } else if (i == r && r < std::min(q[k].m, q[k].n)) {
+          H.kt.bytes += sizeof(T) * (m - r);
+        }
+      }
+    timed_steps_.clear();
+  }
+  std::vector<int> timed_steps_;
+
   // Batched rank-revealing QR: one launch per pivot step until every
   // matrix has stopped (polled every few steps).
   void run_pqr(std::vector<PQRDesc>& q) {
@@ -385,8 +405,15 @@ class Factorizer {
     launch_pqr_init<T>(d, total, states, parts, dmap, st);
     ++launches_;
     int steps = 0;
+    timed_steps_.clear();
     while (steps < kmax) {
+      const bool timed = H.kt.pick("pqr_step");
+      if (timed) {
+        H.kt.mark(st);
+        timed_steps_.push_back(steps);
+      }
       launch_pqr_step<T>(d, total, total, states, parts, dmap, active, steps, eps_, max_m, st);
+      if (timed) H.kt.mark(st);
       ++launches_;
       ++steps;
       if (steps % 16 == 0 && steps < kmax) {
@@ -677,6 +704,7 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
                            hipMemcpyDeviceToHost, st));
   SPAQR_HIP(hipMemcpyAsync(h_rank, d_rank, qe.size() * sizeof(int), hipMemcpyDeviceToHost, st));
   sync();
+  account_pqr(qe, h_rank);
   // new groups, one per (front, owner), appended in front order
   IntPool rp;
   std::vector<RowCopyDesc> rd;
@@ -900,6 +928,7 @@ void Factorizer<T>::step1_all() {
   sync();
   for (int i = 0; i < nflags_; ++i)
     if (h[nr + i]) throw Error(SPAQR_ERANK, "a scaling block is numerically rank deficient");
+  account_pqr(pd, h);
   for (size_t i = 0; i < who.size(); ++i) {
     const int r = h[i];
     RG& gr = G[who[i]];
@@ -1047,6 +1076,7 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
   int* h = static_cast<int*>(H.stage.alloc(std::max<size_t>(1, sel.size()) * sizeof(int)));
   SPAQR_HIP(hipMemcpyAsync(h, d_rank, sel.size() * sizeof(int), hipMemcpyDeviceToHost, st));
   sync();
+  account_pqr(pd, h);
   timer_end();
   for (size_t i = 0; i < ss.size(); ++i) {
     S2& s = ss[i];
@@ -1206,6 +1236,7 @@ void Factorizer<T>::build_apply() {
     int* dp = upload(pool.v);
     std::vector<ApplyOp> ao;
     int mx = 0;
+    double bytes = 0.0, flops = 0.0;
     for (size_t k = i; k < j; ++k) {
       OpRec& o = H.ops[k];
       o.d_s1 = dp + o1[k - i];
@@ -1221,8 +1252,15 @@ void Factorizer<T>::build_apply() {
       a.kind = o.kind;
       ao.push_back(a);
       mx = std::max(mx, o.n1);
+      // algorithmic traffic: factor entries once, vector slots read + written
+      const double n1 = o.n1, n2 = o.n2;
+      const double entries = o.kind == 0 ? n1 * (n1 + 1) / 2 + n1 * n2 : (o.kind == 1 ? n1 * (n1 + 1) / 2 : n1 * n2);
+      bytes += sizeof(T) * entries + 8.0 * (2 * n1 + (o.kind == 0 ? 2 * n2 : 0)) + 4.0 * (n1 + n2);
+      flops += 2.0 * entries;
     }
     ApplyBatch b;
+    b.bytes = bytes;
+    b.flops = flops;
     b.d_ops = upload(ao);
     b.n = (int)ao.size();
     b.max_n1 = mx;
@@ -1270,6 +1308,7 @@ void Factorizer<T>::run() {
   if (forced_ && fpos_ != nforced_) throw Error(SPAQR_EARG, "forced rank list not fully used");
   build_apply();
   sync();
+  H.kt.harvest();
   double ph[5] = {0, 0, 0, 0, merge_s};
   for (auto& t : timers_) {
     float ms = 0.f;
@@ -1316,6 +1355,7 @@ void factorize(Handle& H, double eps, const int* forced, int nforced) {
   H.factored = false;
   SPAQR_HIP(hipStreamSynchronize(H.stream));
   H.arena.reset();
+  H.kt.used = 0;
   H.stage.reset();
   H.ops.clear();
   H.batches.clear();
@@ -1335,10 +1375,17 @@ void apply_op(Handle& H, bool transpose, double* x) {
   const int nb = (int)H.batches.size();
   for (int k = 0; k < nb; ++k) {
     const ApplyBatch& b = H.batches[transpose ? k : nb - 1 - k];
+    const bool timed = H.kt.pick("apply");
+    if (timed) H.kt.mark(H.stream);
     if (H.precision == SPAQR_FP32_FACTOR)
       launch_apply_batch<float>(b.d_ops, b.n, b.max_n1, transpose, x, H.stream);
     else
       launch_apply_batch<double>(b.d_ops, b.n, b.max_n1, transpose, x, H.stream);
+    if (timed) {
+      H.kt.mark(H.stream);
+      H.kt.bytes += b.bytes;
+      H.kt.flops += b.flops;
+    }
   }
 }
 

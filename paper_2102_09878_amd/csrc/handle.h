@@ -27,6 +27,51 @@ struct ApplyBatch {
   const ApplyOp* d_ops = nullptr;
   int n = 0;
   int max_n1 = 0;
+  double bytes = 0.0;  // algorithmic bytes of one application of the batch
+  double flops = 0.0;
+};
+
+// Opt-in per-launch timing of one kernel family with HIP events.
+struct KernelTimer {
+  std::string family;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  int64_t calls = 0, seen = 0;
+  int every = 1;
+  double seconds = 0.0, bytes = 0.0, flops = 0.0;
+
+  bool on(const char* f) const { return !family.empty() && family == f; }
+  // true for the launches that are timed (every `every`-th one of the family)
+  bool pick(const char* f) { return on(f) && (seen++ % every) == 0; }
+  void mark(hipStream_t s) {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      SPAQR_HIP(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    SPAQR_HIP(hipEventRecord(pool[used++], s));
+  }
+  // call after the stream has been synchronised
+  void harvest() {
+    for (size_t i = 0; i + 1 < used; i += 2) {
+      float ms = 0.f;
+      SPAQR_HIP(hipEventElapsedTime(&ms, pool[i], pool[i + 1]));
+      seconds += ms * 1e-3;
+      ++calls;
+    }
+    used = 0;
+  }
+  void reset(const char* f, int ev) {
+    family = f ? f : "";
+    every = ev > 0 ? ev : 1;
+    used = 0;
+    calls = 0;
+    seen = 0;
+    seconds = bytes = flops = 0.0;
+  }
+  ~KernelTimer() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
 };
 
 struct Handle {
@@ -54,6 +99,7 @@ struct Handle {
   std::vector<ApplyBatch> batches;
   std::vector<int> ranks;
   spaqr_stats stats{};
+  KernelTimer kt;
   // solver workspace
   double* d_cg = nullptr;
   size_t cg_elems = 0;

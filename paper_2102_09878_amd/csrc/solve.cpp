@@ -70,6 +70,7 @@ void csne(Handle& H, const double* b, double* x) {
   apply_op(H, false, v.t);
   launch_scale(x, v.t, H.d_D, N, false, H.stream);
   SPAQR_HIP(hipStreamSynchronize(H.stream));
+  H.kt.harvest();
 }
 
 int cgls(Handle& H, const double* b, double tol, int max_iter, double* x, spaqr_cgls_info* info) {
@@ -126,6 +127,7 @@ int cgls(Handle& H, const double* b, double tol, int max_iter, double* x, spaqr_
   atmul(H, v.r, v.t);
   launch_dot(v.t, nullptr, H.d_D, N, v.part, v.sc + SC_TT, st);
   const double tt = std::sqrt(read_scalar(H, v.sc + SC_TT));
+  H.kt.harvest();
   const bool conv = res <= tol;
   if (info) {
     info->iters = it;

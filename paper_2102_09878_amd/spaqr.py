@@ -22,7 +22,7 @@ WINV, WINVT = 0, 1
 
 EXPORTS = ["spaqr_analyze", "spaqr_get_ordering", "spaqr_set_values", "spaqr_factorize",
            "spaqr_factorize_forced", "spaqr_apply", "spaqr_apply_op", "spaqr_cgls", "spaqr_factor_stats",
-           "spaqr_get_ranks", "spaqr_get_op", "spaqr_destroy", "spaqr_last_error"]
+           "spaqr_get_ranks", "spaqr_get_op", "spaqr_time_kernel", "spaqr_destroy", "spaqr_last_error"]
 
 
 class Options(ctypes.Structure):
@@ -43,7 +43,9 @@ class Stats(ctypes.Structure):
                 ("syncs", ctypes.c_int32), ("pad_", ctypes.c_int32), ("mem_factor", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("flops", ctypes.c_double * 5),
                 ("bytes", ctypes.c_double * 5), ("phase_seconds", ctypes.c_double * 5),
-                ("factor_seconds", ctypes.c_double)]
+                ("factor_seconds", ctypes.c_double), ("kernel_calls", ctypes.c_int64),
+                ("kernel_seconds", ctypes.c_double), ("kernel_bytes", ctypes.c_double),
+                ("kernel_flops", ctypes.c_double)]
 
 
 class OpDesc(ctypes.Structure):
@@ -77,6 +79,7 @@ def load(path: str = LIB_PATH):
         "spaqr_factor_stats": [P, ctypes.POINTER(Stats)],
         "spaqr_get_ranks": [P, P, I32, ctypes.POINTER(I32)],
         "spaqr_get_op": [P, I32, ctypes.POINTER(OpDesc), P, P, P, P],
+        "spaqr_time_kernel": [P, ctypes.c_char_p, ctypes.c_int32],
         "spaqr_destroy": [P],
     }
     for name, args in sig.items():
@@ -184,7 +187,8 @@ def spaqr_factor_stats(h):
                 top_rows=s.top_rows, launches=s.launches, syncs=s.syncs, mem_factor=s.mem_factor,
                 device_bytes=s.device_bytes, flops=dict(zip(PHASES, s.flops)),
                 bytes=dict(zip(PHASES, s.bytes)), phase_seconds=dict(zip(PHASES, s.phase_seconds)),
-                factor_seconds=s.factor_seconds)
+                factor_seconds=s.factor_seconds, kernel_calls=s.kernel_calls,
+                kernel_seconds=s.kernel_seconds, kernel_bytes=s.kernel_bytes, kernel_flops=s.kernel_flops)
 
 
 def spaqr_get_ranks(h):
@@ -213,6 +217,11 @@ def spaqr_get_op(h, i):
     if kind == 2:
         out["tau"] = tau[:n2]
     return out
+
+
+def spaqr_time_kernel(h, family, every=1):
+    lib = load()
+    _check(lib, h, lib.spaqr_time_kernel(h, family.encode() if family else None, int(every)))
 
 
 def spaqr_destroy(h):
@@ -274,6 +283,9 @@ class Solver:
 
     def op(self, i):
         return spaqr_get_op(self.h, i)
+
+    def time_kernel(self, family, every=1):
+        spaqr_time_kernel(self.h, family, every)
 
     def close(self):
         if self.h:
