@@ -18,7 +18,8 @@ namespace spaqr {
 namespace {
 
 constexpr int BS = 256;
-constexpr int APPLY_MAX = 6144;  // largest cluster handled by one block (48 KB LDS vector)
+constexpr int APPLY_MAX = 4096;  // largest cluster handled by one block (32 KB LDS vector)
+constexpr int XN_CHUNK = 2048;   // neighbour values staged in LDS per pass (16 KB)
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -92,20 +93,48 @@ __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, i
                                               double* __restrict__ x) {
   const ApplyOp op = ops[blockIdx.x];
   __shared__ double t[APPLY_MAX];
+  __shared__ double xn[XN_CHUNK];
   __shared__ double sh[4];
   const int tid = threadIdx.x;
   const int n1 = op.n1;
   const T* R = static_cast<const T*>(op.R);
+  if (n1 <= 0) return;  // uniform over the block
   for (int i = tid; i < n1; i += BS) t[i] = x[op.s1[i]];
   __syncthreads();
   if (op.kind == 0) {  // eliminate
     const int cN = op.n2;
     const T* RN = R + (int64_t)n1 * op.ld;
     if (!transpose) {
-      for (int i = tid; i < n1; i += BS) {
-        double acc = 0.0;
-        for (int c = 0; c < cN; ++c) acc += (double)RN[i + c * op.ld] * x[op.s2[c]];
-        t[i] -= acc;
+      // t -= R_sN x_N.  x_N is staged in LDS chunk by chunk; when the
+      // cluster has fewer rows than threads, threads split the columns into
+      // `ns` slices and the slices are summed at the end.
+      const int ns = n1 >= BS ? 1 : BS / n1;
+      const int my_i = n1 >= BS ? 0 : tid % n1, my_s = n1 >= BS ? 0 : tid / n1;
+      double acc_s = 0.0;
+      for (int cb = 0; cb < cN; cb += XN_CHUNK) {
+        const int ce = min(cN, cb + XN_CHUNK);
+        __syncthreads();
+        for (int c = cb + tid; c < ce; c += BS) xn[c - cb] = x[op.s2[c]];
+        __syncthreads();
+        if (n1 >= BS) {
+          for (int i = tid; i < n1; i += BS) {
+            double acc = 0.0;
+            for (int c = cb; c < ce; ++c) acc += (double)RN[i + (int64_t)c * op.ld] * xn[c - cb];
+            t[i] -= acc;
+          }
+        } else if (my_s < ns) {
+          for (int c = cb + my_s; c < ce; c += ns) acc_s += (double)RN[my_i + (int64_t)c * op.ld] * xn[c - cb];
+        }
+      }
+      if (n1 < BS) {
+        __syncthreads();
+        if (my_s < ns) xn[tid] = acc_s;
+        __syncthreads();
+        if (tid < n1) {
+          double a = 0.0;
+          for (int s = 0; s < ns; ++s) a += xn[s * n1 + tid];
+          t[tid] -= a;
+        }
       }
       __syncthreads();
       trsv_upper(R, op.ld, n1, t);
@@ -113,13 +142,23 @@ __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, i
     } else {
       trsv_upper_t(R, op.ld, n1, t);
       for (int i = tid; i < n1; i += BS) x[op.s1[i]] = t[i];
-      const int w = tid >> 6, lane = tid & 63;
-      for (int c = w; c < cN; c += 4) {
-        const T* col = RN + c * op.ld;
-        double acc = 0.0;
-        for (int i = lane; i < n1; i += 64) acc += (double)col[i] * t[i];
-        acc = wave_sum(acc);
-        if (lane == 0) atomicAdd(x + op.s2[c], -acc);
+      if (cN >= BS) {
+        // one column per thread: each thread streams its own column of R_sN
+        for (int c = tid; c < cN; c += BS) {
+          const T* col = RN + (int64_t)c * op.ld;
+          double acc = 0.0;
+          for (int i = 0; i < n1; ++i) acc += (double)col[i] * t[i];
+          atomicAdd(x + op.s2[c], -acc);
+        }
+      } else {
+        const int w = tid >> 6, lane = tid & 63;
+        for (int c = w; c < cN; c += 4) {
+          const T* col = RN + (int64_t)c * op.ld;
+          double acc = 0.0;
+          for (int i = lane; i < n1; i += 64) acc += (double)col[i] * t[i];
+          acc = wave_sum(acc);
+          if (lane == 0) atomicAdd(x + op.s2[c], -acc);
+        }
       }
     }
   } else if (op.kind == 1) {  // scale

@@ -868,6 +868,7 @@ void Factorizer<T>::scale_all() {
   IntPool tp;
   std::vector<TrsmDesc> td;
   std::vector<size_t> td_map;
+  int td_rows = 0;
   for (int g : live_groups()) {
     RG& gr = G[g];
     for (int q : gr.clus) {
@@ -881,13 +882,14 @@ void Factorizer<T>::scale_all() {
       d.c = (int)C[q].slots.size();
       td_map.push_back(tp.add(colmap(gr, C[q].slots, true)));
       td.push_back(d);
+      td_rows = std::max(td_rows, d.nrows);
       flops_[PH_SCALE] += (double)gr.nrows * d.c * d.c;
       bytes_[PH_SCALE] += 2.0 * sizeof(T) * gr.nrows * d.c;
     }
   }
   int* dtp = upload(tp.v);
   for (size_t i = 0; i < td.size(); ++i) td[i].colmap = dtp + td_map[i];
-  launch_trsm<T>(upload(td), (int)td.size(), st);
+  launch_trsm<T>(upload(td), (int)td.size(), td_rows, st);
   ++launches_;
   timer_end();
   // rank-deficiency flags are read together with the step-1 ranks

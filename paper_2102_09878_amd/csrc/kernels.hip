@@ -49,21 +49,6 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
-// Householder scalars for x = [alpha; tail], ||tail||^2 = xn2.
-__device__ __forceinline__ void house_scalars(double alpha, double xn2, double& beta, double& tau,
-                                              double& scal) {
-  if (xn2 == 0.0) {
-    beta = alpha;
-    tau = 0.0;
-    scal = 1.0;
-  } else {
-    const double s = alpha < 0.0 ? -1.0 : 1.0;
-    beta = -s * sqrt(alpha * alpha + xn2);
-    tau = (beta - alpha) / beta;
-    scal = 1.0 / (alpha - beta);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // gather
 // ---------------------------------------------------------------------------
@@ -110,20 +95,49 @@ __global__ void k_scatter_csr(T* __restrict__ base, const int64_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// B <- B R^-1 (R upper triangular), rows in parallel
+// B <- B R^-1 (R upper triangular).  One thread per row of B, grid over
+// (descriptor, chunk of BS rows).  Columns are solved left-looking in
+// register blocks of TRSM_NB: the block's entries are loaded, reduced by
+// the already solved columns (re-read from B, coalesced over rows), then
+// solved in registers.  R is read at block-uniform addresses.
 // ---------------------------------------------------------------------------
+constexpr int TRSM_NB = 16;
+
 template <typename T>
 __global__ __launch_bounds__(BS) void k_trsm(const TrsmDesc* __restrict__ D) {
   const TrsmDesc d = D[blockIdx.x];
+  if ((int)blockIdx.y * BS >= d.nrows) return;  // whole block
+  const int r = blockIdx.y * BS + threadIdx.x;
+  const bool live = r < d.nrows;
   T* B = static_cast<T*>(d.B);
   const T* R = static_cast<const T*>(d.R);
-  for (int r = threadIdx.x; r < d.nrows; r += BS) {
-    for (int j = 0; j < d.c; ++j) {
-      T* bj = B + r + (int64_t)d.colmap[j] * d.ldb;
-      double acc = *bj;
-      const T* rc = R + (int64_t)j * d.ldr;
-      for (int i = 0; i < j; ++i) acc -= (double)B[r + (int64_t)d.colmap[i] * d.ldb] * (double)rc[i];
-      *bj = static_cast<T>(acc / (double)rc[j]);
+  for (int jb = 0; jb < d.c; jb += TRSM_NB) {
+    const int nb = min(TRSM_NB, d.c - jb);
+    double acc[TRSM_NB];
+#pragma unroll
+    for (int k = 0; k < TRSM_NB; ++k)
+      acc[k] = (live && k < nb) ? (double)B[r + (int64_t)d.colmap[jb + k] * d.ldb] : 0.0;
+    for (int i = 0; i < jb; ++i) {
+      const double bi = live ? (double)B[r + (int64_t)d.colmap[i] * d.ldb] : 0.0;
+      const T* ri = R + i + (int64_t)jb * d.ldr;
+#pragma unroll
+      for (int k = 0; k < TRSM_NB; ++k)
+        if (k < nb) acc[k] -= bi * (double)ri[k * d.ldr];
+    }
+#pragma unroll
+    for (int k = 0; k < TRSM_NB; ++k) {
+      if (k < nb) {
+        const T* rk = R + (jb + k) + (int64_t)jb * d.ldr;
+        acc[k] /= (double)rk[k * d.ldr];
+#pragma unroll
+        for (int k2 = k + 1; k2 < TRSM_NB; ++k2)
+          if (k2 < nb) acc[k2] -= acc[k] * (double)rk[k2 * d.ldr];
+      }
+    }
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < TRSM_NB; ++k)
+        if (k < nb) B[r + (int64_t)d.colmap[jb + k] * d.ldb] = static_cast<T>(acc[k]);
     }
   }
 }
@@ -240,9 +254,9 @@ void launch_scatter_csr(T* base, const int64_t* dst, const double* ahat, int64_t
 }
 
 template <typename T>
-void launch_trsm(const TrsmDesc* d_desc, int n, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_trsm<T>, dim3(n), dim3(BS), 0, s, d_desc);
+void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, hipStream_t s) {
+  if (n <= 0 || max_rows <= 0) return;
+  hipLaunchKernelGGL(k_trsm<T>, dim3(n, (max_rows + BS - 1) / BS), dim3(BS), 0, s, d_desc);
   SPAQR_HIP(hipGetLastError());
 }
 
@@ -278,7 +292,7 @@ void launch_scatter(const ScatterDesc* d_desc, int n, hipStream_t s) {
 #define SPAQR_INST(T)                                                                          \
   template void launch_gather<T>(const GatherDesc*, int, int, hipStream_t);                    \
   template void launch_scatter_csr<T>(T*, const int64_t*, const double*, int64_t, hipStream_t); \
-  template void launch_trsm<T>(const TrsmDesc*, int, hipStream_t);                             \
+  template void launch_trsm<T>(const TrsmDesc*, int, int, hipStream_t);                             \
   template void launch_owner<T>(const OwnerDesc*, int, hipStream_t);                           \
   template void launch_rowcopy<T>(const RowCopyDesc*, int, int, hipStream_t);                         \
   template void launch_extract<T>(const ExtractDesc*, int, hipStream_t);                       \

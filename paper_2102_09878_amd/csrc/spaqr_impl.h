@@ -291,7 +291,7 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h_desc, const QR
 // chunks of PQR_CW over work-groups).  The caller provides device scratch:
 // states (2 per matrix), parts (2 per chunk), bmap (one int2 per chunk) and
 // an `active` counter; h_desc must already carry blk0/nblk.
-constexpr int PQR_CW = 64;
+constexpr int PQR_CW = 8;
 template <typename T>
 void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPart* parts,
                      const int2* bmap, hipStream_t s);
@@ -302,7 +302,7 @@ void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRSta
 template <typename T>
 void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int steps, hipStream_t s);
 template <typename T>
-void launch_trsm(const TrsmDesc* d_desc, int n, hipStream_t s);
+void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, hipStream_t s);
 template <typename T>
 void launch_owner(const OwnerDesc* d_desc, int n, hipStream_t s);
 template <typename T>
