@@ -102,11 +102,13 @@ typedef struct {
   int32_t level;  /* tree level being processed when the op was created                   */
 } spaqr_op_desc;
 
-/* Analysis (host only, no GPU needed): column scaling D (Section 2.7),
+/* Analysis (host only, no GPU needed): column norms of the given values
+ * (Algorithm 1 scales every column to unit 2-norm before partitioning),
  * geometric nested dissection with interfaces and their hierarchy
- * (Section 2.2, Figure 3), row matching (column j <-> row j, the Laplacian
- * row of cell j) and max-norm assignment of the other rows (Section 2.2),
- * and the ||A||_2 estimate of the CGLS stopping test.
+ * (Section 2.2), row matching (column j <-> row j, the Laplacian row of
+ * cell j) and max-norm assignment of the other rows (Section 2.2).  The
+ * device copy of the scaled matrix and the ||A||_2 estimate of the CGLS
+ * stopping test are made by device kernels on first GPU use.
  * Errors: SPAQR_EARG for M < N, N < 1, a malformed CSR, an empty column, a
  * grid that does not match N or is too small for the depth, or a row that
  * couples two sibling subtrees.  On success *out owns a new handle. */
@@ -120,8 +122,10 @@ int spaqr_analyze(const int64_t* row_ptr, const int32_t* col_idx, const double* 
 int spaqr_get_ordering(spaqr_handle h, int32_t* col_perm, int32_t* row_owner);
 
 /* Replace the nonzero values (same pattern) from a device buffer of nnz
- * doubles; the analysis (ordering, owners) is kept, column norms are
- * recomputed.  Any factor is invalidated. */
+ * doubles in CSR order; the analysis (ordering, row owners) is kept, the
+ * column scaling (Algorithm 1) and the ||A||_2 estimate are recomputed on
+ * the device.  Any factor is invalidated.  SPAQR_EARG if a column becomes
+ * zero. */
 int spaqr_set_values(spaqr_handle h, const double* vals_dev);
 
 /* Numeric factorization with tolerance eps >= 0 (Algorithm 1).  Ranks of
@@ -149,6 +153,23 @@ int spaqr_apply_op(spaqr_handle h, int32_t op, const double* in_dev, double* out
  * SPAQR_NOCONV when max_iter was reached. */
 int spaqr_cgls(spaqr_handle h, const double* b_dev, double tol, int32_t max_iter, double* x_dev,
                spaqr_cgls_info* info);
+
+/* Adjoint of the least-squares solution x = argmin ||A x - b|| for a loss
+ * with gradient g = dL/dx: solves A^T A lambda = g by conjugate gradients
+ * preconditioned with the factor of the current values, M^-1 =
+ * D^-1 W^-1 W^-T D^-1 (A^T A ~ D W^T W D, Section 2.7), and forms
+ *   grad_b[i]    = (A lambda)_i,
+ *   grad_vals[e] = r_i lambda_j - (A lambda)_i x_j  (entry e at row i, col j),
+ * with r = b - A x.  x_dev, g_dev: N doubles; b_dev, grad_b_dev: M doubles;
+ * grad_vals_dev: nnz doubles in CSR order; lambda_dev: N doubles.  Any of
+ * grad_b_dev, grad_vals_dev, lambda_dev may be NULL (grad_vals needs x and
+ * b).  Stops when ||g - A^T A lambda|| <= tol ||g|| (recurrence); info gets
+ * iterations, the true relative residual (residual), the recurrence one
+ * (paper_residual) and seconds.  SPAQR_ESTATE before a factorization,
+ * SPAQR_NOCONV at max_iter (outputs still written). */
+int spaqr_adjoint(spaqr_handle h, const double* x_dev, const double* b_dev, const double* g_dev,
+                  double tol, int32_t max_iter, double* grad_b_dev, double* grad_vals_dev,
+                  double* lambda_dev, spaqr_cgls_info* info);
 
 /* Statistics of the last factorization (Section 4.2 quantities, the
  * per-phase ledger, launch and synchronisation counts). */

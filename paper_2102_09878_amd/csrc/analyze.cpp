@@ -183,26 +183,6 @@ void rescale_values(Plan& P, const double* vals) {
   }
   P.ahat.resize(P.nnz);
   for (int64_t e = 0; e < P.nnz; ++e) P.ahat[e] = P.vals[e] / P.D[P.col_idx[e]];
-  // ||A||_2 by 30 power steps on A^T A from the all-ones vector
-  std::vector<double> v(P.N, 1.0 / std::sqrt((double)P.N)), u(P.M), w(P.N);
-  double lam = 0.0;
-  for (int it = 0; it < 30; ++it) {
-    for (int64_t r = 0; r < P.M; ++r) {
-      double acc = 0.0;
-      for (int64_t e = P.row_ptr[r]; e < P.row_ptr[r + 1]; ++e) acc += P.vals[e] * v[P.col_idx[e]];
-      u[r] = acc;
-    }
-    std::fill(w.begin(), w.end(), 0.0);
-    for (int64_t r = 0; r < P.M; ++r)
-      for (int64_t e = P.row_ptr[r]; e < P.row_ptr[r + 1]; ++e) w[P.col_idx[e]] += P.vals[e] * u[r];
-    double nw = 0.0;
-    for (double x : w) nw += x * x;
-    nw = std::sqrt(nw);
-    lam = nw;
-    if (nw == 0.0) break;
-    for (int64_t j = 0; j < P.N; ++j) v[j] = w[j] / nw;
-  }
-  P.normA = std::sqrt(lam);
 }
 
 void analyze_plan(Plan& P, const int64_t* row_ptr, const int32_t* col_idx, const double* vals,

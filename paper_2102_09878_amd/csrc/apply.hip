@@ -3,10 +3,13 @@
 // W is a product of elementary ops (Section 2.7): eliminations
 // [R_ss R_sN; 0 I], scalings R_pp and sparsifications Q_pp = H_1..H_r.
 // W^-1 is applied op by op from the last to the first, W^-T from the first
-// to the last with transposes.  Ops created in one round touch disjoint
-// slots, so a round is one batched launch (one block per op).  Factors may
-// be FP32; every accumulation is FP64, so the preconditioner stays a fixed
-// linear operator for CGLS.
+// to the last with transposes.  Ops created in one round never write a slot
+// another op of the round reads, so a round is one batched launch (one
+// block per op); only the neighbour updates x_N -= R_sN^T x_s of W^-T can
+// meet on a shared neighbour, and they go through a staging buffer summed
+// per slot in op order, which keeps every application bit-reproducible.
+// Factors may be FP32; every accumulation is FP64, so the preconditioner
+// stays a fixed linear operator for CGLS.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -90,7 +93,7 @@ __device__ void trsv_upper_t(const T* __restrict__ R, int64_t ld, int n, double*
 
 template <typename T>
 __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, int transpose,
-                                              double* __restrict__ x) {
+                                              double* __restrict__ x, double* __restrict__ stage) {
   const ApplyOp op = ops[blockIdx.x];
   __shared__ double t[APPLY_MAX];
   __shared__ double xn[XN_CHUNK];
@@ -142,13 +145,16 @@ __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, i
     } else {
       trsv_upper_t(R, op.ld, n1, t);
       for (int i = tid; i < n1; i += BS) x[op.s1[i]] = t[i];
+      // R_sN^T t to the staging buffer; neighbours shared by several ops
+      // of the round are summed afterwards in op order
+      double* out = stage + op.nstage;
       if (cN >= BS) {
         // one column per thread: each thread streams its own column of R_sN
         for (int c = tid; c < cN; c += BS) {
           const T* col = RN + (int64_t)c * op.ld;
           double acc = 0.0;
           for (int i = 0; i < n1; ++i) acc += (double)col[i] * t[i];
-          atomicAdd(x + op.s2[c], -acc);
+          out[c] = acc;
         }
       } else {
         const int w = tid >> 6, lane = tid & 63;
@@ -157,7 +163,7 @@ __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, i
           double acc = 0.0;
           for (int i = lane; i < n1; i += 64) acc += (double)col[i] * t[i];
           acc = wave_sum(acc);
-          if (lane == 0) atomicAdd(x + op.s2[c], -acc);
+          if (lane == 0) out[c] = acc;
         }
       }
     }
@@ -184,6 +190,17 @@ __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, i
   }
 }
 
+// x[nslots[k]] -= sum of stage[noff[e]] for e in [nptr[k], nptr[k+1]), in order
+__global__ void k_apply_nsum(const int* __restrict__ nslots, const int* __restrict__ nptr,
+                             const int* __restrict__ noff, int n, const double* __restrict__ stage,
+                             double* __restrict__ x) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double acc = 0.0;
+  for (int e = nptr[k]; e < nptr[k + 1]; ++e) acc += stage[noff[e]];
+  x[nslots[k]] -= acc;
+}
+
 __global__ void k_spmv(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                        const double* __restrict__ val, const double* __restrict__ x,
                        double* __restrict__ y, int64_t rows) {
@@ -198,10 +215,17 @@ __global__ void k_spmv(const int64_t* __restrict__ ptr, const int32_t* __restric
 
 template <typename T>
 void launch_apply_batch(const ApplyOp* d_ops, int n, int max_n1, bool transpose, double* x,
-                        hipStream_t s) {
+                        double* stage, hipStream_t s) {
   if (n <= 0) return;
   if (max_n1 > APPLY_MAX) throw Error(SPAQR_EARG, "cluster too large for the apply kernel");
-  hipLaunchKernelGGL(k_apply<T>, dim3(n), dim3(BS), 0, s, d_ops, transpose ? 1 : 0, x);
+  hipLaunchKernelGGL(k_apply<T>, dim3(n), dim3(BS), 0, s, d_ops, transpose ? 1 : 0, x, stage);
+  SPAQR_HIP(hipGetLastError());
+}
+
+void launch_apply_nsum(const int* nslots, const int* nptr, const int* noff, int n, const double* stage,
+                       double* x, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_apply_nsum, dim3((n + BS - 1) / BS), dim3(BS), 0, s, nslots, nptr, noff, n, stage, x);
   SPAQR_HIP(hipGetLastError());
 }
 
@@ -213,7 +237,7 @@ void launch_spmv(const int64_t* ptr, const int32_t* idx, const double* val, cons
   SPAQR_HIP(hipGetLastError());
 }
 
-template void launch_apply_batch<double>(const ApplyOp*, int, int, bool, double*, hipStream_t);
-template void launch_apply_batch<float>(const ApplyOp*, int, int, bool, double*, hipStream_t);
+template void launch_apply_batch<double>(const ApplyOp*, int, int, bool, double*, double*, hipStream_t);
+template void launch_apply_batch<float>(const ApplyOp*, int, int, bool, double*, double*, hipStream_t);
 
 }  // namespace spaqr

@@ -74,17 +74,10 @@ int spaqr_set_values(spaqr_handle h, const double* vals_dev) {
     if (!h || !vals_dev) throw spaqr::Error(SPAQR_EARG, "null argument");
     spaqr::Handle& H = h->h;
     H.ensure_device();
-    std::vector<double> v(H.P.nnz);
-    SPAQR_HIP(hipMemcpyAsync(v.data(), vals_dev, v.size() * sizeof(double), hipMemcpyDeviceToHost,
-                             H.stream));
-    SPAQR_HIP(hipStreamSynchronize(H.stream));
-    spaqr::rescale_values(H.P, v.data());
-    std::vector<double> at(H.P.nnz);
-    for (int64_t e = 0; e < H.P.nnz; ++e) at[e] = H.P.ahat[H.P.at_src[e]];
-    SPAQR_HIP(hipMemcpy(H.d_ahat, H.P.ahat.data(), H.P.nnz * sizeof(double), hipMemcpyHostToDevice));
-    SPAQR_HIP(hipMemcpy(H.d_ahatT, at.data(), H.P.nnz * sizeof(double), hipMemcpyHostToDevice));
-    SPAQR_HIP(hipMemcpy(H.d_D, H.P.D.data(), H.P.N * sizeof(double), hipMemcpyHostToDevice));
     H.factored = false;
+    SPAQR_HIP(hipMemcpyAsync(H.d_vals, vals_dev, H.P.nnz * sizeof(double), hipMemcpyDeviceToDevice,
+                             H.stream));
+    spaqr::scale_values(H);
     return SPAQR_OK;
   });
 }
@@ -134,6 +127,17 @@ int spaqr_cgls(spaqr_handle h, const double* b_dev, double tol, int32_t max_iter
   return guard(h, [&]() -> int {
     if (!h || !b_dev || !x_dev) throw spaqr::Error(SPAQR_EARG, "null argument");
     return spaqr::cgls(h->h, b_dev, tol, max_iter, x_dev, info);
+  });
+}
+
+int spaqr_adjoint(spaqr_handle h, const double* x_dev, const double* b_dev, const double* g_dev,
+                  double tol, int32_t max_iter, double* grad_b_dev, double* grad_vals_dev,
+                  double* lambda_dev, spaqr_cgls_info* info) {
+  return guard(h, [&]() -> int {
+    if (!h || !g_dev) throw spaqr::Error(SPAQR_EARG, "null argument");
+    if (grad_vals_dev && (!x_dev || !b_dev)) throw spaqr::Error(SPAQR_EARG, "grad_vals needs x and b");
+    return spaqr::adjoint(h->h, x_dev, b_dev, g_dev, tol, max_iter, grad_b_dev, grad_vals_dev, lambda_dev,
+                          info);
   });
 }
 

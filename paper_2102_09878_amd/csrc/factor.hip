@@ -104,10 +104,12 @@ void Handle::release_device() {
   if (!dev_ready) return;
   (void)hipStreamSynchronize(stream);
   for (void* p : {(void*)d_ahat, (void*)d_rp, (void*)d_ci, (void*)d_ahatT, (void*)d_atp, (void*)d_ati,
-                  (void*)d_init_dst, (void*)d_D, (void*)d_cg})
+                  (void*)d_init_dst, (void*)d_D, (void*)d_cg, (void*)d_vals, (void*)d_atsrc, (void*)d_flag})
     if (p) (void)hipFree(p);
   if (h_sc) (void)hipHostFree(h_sc);
-  d_ahat = d_ahatT = d_D = d_cg = nullptr;
+  d_ahat = d_ahatT = d_D = d_cg = d_vals = nullptr;
+  d_atsrc = nullptr;
+  d_flag = nullptr;
   d_rp = d_atp = nullptr;
   d_ci = d_ati = nullptr;
   d_init_dst = nullptr;
@@ -136,16 +138,18 @@ void Handle::ensure_device() {
   plan_bytes = 0;
   d_rp = dcopy(P.row_ptr, plan_bytes);
   d_ci = dcopy(P.col_idx, plan_bytes);
-  d_ahat = dcopy(P.ahat, plan_bytes);
-  std::vector<double> at(P.nnz);
-  for (int64_t e = 0; e < P.nnz; ++e) at[e] = P.ahat[P.at_src[e]];
-  d_ahatT = dcopy(at, plan_bytes);
+  d_vals = dcopy(P.vals, plan_bytes);
   d_atp = dcopy(P.at_ptr, plan_bytes);
   d_ati = dcopy(P.at_idx, plan_bytes);
+  d_atsrc = dcopy(P.at_src, plan_bytes);
   d_init_dst = dcopy(P.init_dst, plan_bytes);
-  d_D = dcopy(P.D, plan_bytes);
+  d_ahat = dcopy(std::vector<double>(P.nnz), plan_bytes);
+  d_ahatT = dcopy(std::vector<double>(P.nnz), plan_bytes);
+  d_D = dcopy(std::vector<double>(P.N), plan_bytes);
+  d_flag = dcopy(std::vector<int>(1), plan_bytes);
   SPAQR_HIP(hipHostMalloc((void**)&h_sc, 64 * sizeof(double), hipHostMallocDefault));
   dev_ready = true;
+  scale_values(*this);
 }
 
 // ---------------------------------------------------------------------------
@@ -1224,6 +1228,7 @@ template <typename T>
 void Factorizer<T>::build_apply() {
   H.batches.clear();
   size_t i = 0;
+  int64_t max_stage = 0;
   while (i < H.ops.size()) {
     size_t j = i;
     while (j < H.ops.size() && H.ops[j].level == H.ops[i].level && H.ops[j].phase == H.ops[i].phase &&
@@ -1239,6 +1244,10 @@ void Factorizer<T>::build_apply() {
     std::vector<ApplyOp> ao;
     int mx = 0;
     double bytes = 0.0, flops = 0.0;
+    // neighbour contributions of the eliminations (W^-T): staging offsets
+    // per op, and per touched slot the list of offsets in op order
+    int nstage = 0;
+    std::vector<std::pair<int, int>> contrib;  // (slot, staging offset), op order within a slot
     for (size_t k = i; k < j; ++k) {
       OpRec& o = H.ops[k];
       o.d_s1 = dp + o1[k - i];
@@ -1252,6 +1261,12 @@ void Factorizer<T>::build_apply() {
       a.n1 = o.n1;
       a.n2 = o.n2;
       a.kind = o.kind;
+      a.nstage = 0;
+      if (o.kind == 0 && o.n1 > 0 && o.n2 > 0) {
+        a.nstage = nstage;
+        for (int c = 0; c < o.n2; ++c) contrib.push_back({o.s2[c], nstage + c});
+        nstage += o.n2;
+      }
       ao.push_back(a);
       mx = std::max(mx, o.n1);
       // algorithmic traffic: factor entries once, vector slots read + written
@@ -1266,9 +1281,28 @@ void Factorizer<T>::build_apply() {
     b.d_ops = upload(ao);
     b.n = (int)ao.size();
     b.max_n1 = mx;
+    if (!contrib.empty()) {
+      std::stable_sort(contrib.begin(), contrib.end(),
+                       [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first < b.first; });
+      std::vector<int> ns, np{0}, no;
+      for (size_t e = 0; e < contrib.size(); ++e) {
+        if (e == 0 || contrib[e].first != contrib[e - 1].first) {
+          if (e) np.push_back((int)e);
+          ns.push_back(contrib[e].first);
+        }
+        no.push_back(contrib[e].second);
+      }
+      np.push_back((int)contrib.size());
+      b.d_nslots = upload(ns);
+      b.d_nptr = upload(np);
+      b.d_noff = upload(no);
+      b.n_nslots = (int)ns.size();
+      max_stage = std::max<int64_t>(max_stage, nstage);
+    }
     H.batches.push_back(b);
     i = j;
   }
+  H.d_nstage = max_stage > 0 ? static_cast<double*>(H.arena.alloc(max_stage * sizeof(double))) : nullptr;
 }
 
 template <typename T>
@@ -1380,9 +1414,11 @@ void apply_op(Handle& H, bool transpose, double* x) {
     const bool timed = H.kt.pick("apply");
     if (timed) H.kt.mark(H.stream);
     if (H.precision == SPAQR_FP32_FACTOR)
-      launch_apply_batch<float>(b.d_ops, b.n, b.max_n1, transpose, x, H.stream);
+      launch_apply_batch<float>(b.d_ops, b.n, b.max_n1, transpose, x, H.d_nstage, H.stream);
     else
-      launch_apply_batch<double>(b.d_ops, b.n, b.max_n1, transpose, x, H.stream);
+      launch_apply_batch<double>(b.d_ops, b.n, b.max_n1, transpose, x, H.d_nstage, H.stream);
+    if (transpose && b.n_nslots > 0)
+      launch_apply_nsum(b.d_nslots, b.d_nptr, b.d_noff, b.n_nslots, H.d_nstage, x, H.stream);
     if (timed) {
       H.kt.mark(H.stream);
       H.kt.bytes += b.bytes;

@@ -27,6 +27,12 @@ struct ApplyBatch {
   const ApplyOp* d_ops = nullptr;
   int n = 0;
   int max_n1 = 0;
+  // W^-T of eliminations: neighbour slots touched by the batch, each with
+  // the staging offsets of its contributions in op order (CSR)
+  const int* d_nslots = nullptr;
+  const int* d_nptr = nullptr;
+  const int* d_noff = nullptr;
+  int n_nslots = 0;
   double bytes = 0.0;  // algorithmic bytes of one application of the batch
   double flops = 0.0;
 };
@@ -89,6 +95,10 @@ struct Handle {
   int32_t* d_ati = nullptr;
   int64_t* d_init_dst = nullptr;
   double* d_D = nullptr;
+  double* d_vals = nullptr;     // values of A as given (CSR order)
+  int64_t* d_atsrc = nullptr;   // CSR entry of each transposed entry
+  int* d_flag = nullptr;
+  double normA = 0.0;           // ||A||_2 estimate of the current values
   size_t plan_bytes = 0;
   // factor
   Arena arena;
@@ -97,6 +107,7 @@ struct Handle {
   int precision = SPAQR_FP64;
   std::vector<OpRec> ops;
   std::vector<ApplyBatch> batches;
+  double* d_nstage = nullptr;  // contributions R_sN^T x_s of one batch (arena)
   std::vector<int> ranks;
   spaqr_stats stats{};
   KernelTimer kt;
@@ -114,5 +125,10 @@ void factorize(Handle& H, double eps, const int* forced, int nforced);
 void apply_op(Handle& H, bool transpose, double* x_dev);
 int cgls(Handle& H, const double* b, double tol, int max_iter, double* x, spaqr_cgls_info* info);
 void csne(Handle& H, const double* b, double* x);
+// Column scaling of the current device values d_vals: D, Ahat, Ahat^T and
+// the ||A||_2 estimate, all on the device.
+void scale_values(Handle& H);
+int adjoint(Handle& H, const double* x, const double* b, const double* g, double tol, int max_iter,
+            double* grad_b, double* grad_vals, double* lambda, spaqr_cgls_info* info);
 
 }  // namespace spaqr

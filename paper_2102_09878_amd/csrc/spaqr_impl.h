@@ -83,7 +83,6 @@ struct Plan {
   std::vector<int64_t> at_ptr;
   std::vector<int32_t> at_idx;
   std::vector<int64_t> at_src;      // CSR entry index of each A^T entry
-  double normA = 0.0;
 };
 
 void analyze_plan(Plan& P, const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
@@ -255,7 +254,8 @@ struct ApplyOp {
   const int* s2;       // slots of the neighbours (eliminate)
   int64_t ld;
   int n1, n2;          // eliminate: c_s, c_N; scale: c_p, 0; sparsify: c_p, r
-  int kind, pad_;
+  int kind;
+  int nstage;          // eliminate, W^-T: offset of R_sN^T x_s in the staging buffer
 };
 
 // ---------------------------------------------------------------------------
@@ -312,9 +312,15 @@ void launch_extract(const ExtractDesc* d_desc, int n, hipStream_t s);
 template <typename T>
 void launch_scatter(const ScatterDesc* d_desc, int n, hipStream_t s);
 
+// One round of W^-1 or W^-T ops.  In W^-T an elimination writes
+// R_sN^T x_s to stage + nstage instead of updating x; launch_apply_nsum then
+// subtracts, per neighbour slot, its contributions summed in op order
+// (deterministic, no atomics).
 template <typename T>
 void launch_apply_batch(const ApplyOp* d_ops, int n, int max_n1, bool transpose, double* x,
-                        hipStream_t s);
+                        double* stage, hipStream_t s);
+void launch_apply_nsum(const int* nslots, const int* nptr, const int* noff, int n, const double* stage,
+                       double* x, hipStream_t s);
 
 void launch_spmv(const int64_t* ptr, const int32_t* idx, const double* val, const double* x,
                  double* y, int64_t rows, hipStream_t s);

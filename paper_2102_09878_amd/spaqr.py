@@ -22,7 +22,8 @@ WINV, WINVT = 0, 1
 
 EXPORTS = ["spaqr_analyze", "spaqr_get_ordering", "spaqr_set_values", "spaqr_factorize",
            "spaqr_factorize_forced", "spaqr_apply", "spaqr_apply_op", "spaqr_cgls", "spaqr_factor_stats",
-           "spaqr_get_ranks", "spaqr_get_op", "spaqr_time_kernel", "spaqr_destroy", "spaqr_last_error"]
+           "spaqr_get_ranks", "spaqr_get_op", "spaqr_time_kernel", "spaqr_adjoint", "spaqr_destroy",
+           "spaqr_last_error"]
 
 
 class Options(ctypes.Structure):
@@ -80,6 +81,7 @@ def load(path: str = LIB_PATH):
         "spaqr_get_ranks": [P, P, I32, ctypes.POINTER(I32)],
         "spaqr_get_op": [P, I32, ctypes.POINTER(OpDesc), P, P, P, P],
         "spaqr_time_kernel": [P, ctypes.c_char_p, ctypes.c_int32],
+        "spaqr_adjoint": [P, P, P, P, D, I32, P, P, P, ctypes.POINTER(CglsInfo)],
         "spaqr_destroy": [P],
     }
     for name, args in sig.items():
@@ -179,6 +181,21 @@ def spaqr_cgls(h, b_dev, x_dev, tol=1e-10, max_iter=200):
                 paper_residual=info.paper_residual, norm_a=info.norm_a, seconds=info.seconds)
 
 
+def spaqr_adjoint(h, x_dev, b_dev, g_dev, grad_b_dev=None, grad_vals_dev=None, lambda_dev=None, tol=1e-12,
+                  max_iter=500):
+    lib = load()
+    info = CglsInfo()
+
+    def opt(t):
+        return None if t is None else _ptr(_dev_f64(t))
+
+    rc = lib.spaqr_adjoint(h, opt(x_dev), opt(b_dev), _ptr(_dev_f64(g_dev)), float(tol), int(max_iter),
+                           opt(grad_b_dev), opt(grad_vals_dev), opt(lambda_dev), ctypes.byref(info))
+    _check(lib, h, rc, allow=(OK, NOCONV))
+    return dict(iters=info.iters, converged=bool(info.converged), residual=info.residual,
+                recurrence_residual=info.paper_residual, seconds=info.seconds)
+
+
 def spaqr_factor_stats(h):
     lib = load()
     s = Stats()
@@ -237,6 +254,8 @@ class Solver:
     def __init__(self, row_ptr, col_idx, vals, M, N, grid, depth=0, skip=-1, sep_width=0,
                  precision="fp64", device=0):
         self.M, self.N = int(M), int(N)
+        self.nnz = int(len(col_idx))
+        self.version = 0  # bumped whenever the values or the factor change
         prec = {"fp64": FP64, "fp32": FP32_FACTOR}[precision]
         self.h = spaqr_analyze(row_ptr, col_idx, vals, M, N, grid, depth, skip, sep_width, prec, device)
 
@@ -249,12 +268,14 @@ class Solver:
         return spaqr_get_ordering(self.h, self.M, self.N)
 
     def factorize(self, eps, ranks=None):
+        self.version += 1
         if ranks is None:
             spaqr_factorize(self.h, eps)
         else:
             spaqr_factorize_forced(self.h, eps, ranks)
 
     def set_values(self, vals_dev):
+        self.version += 1
         spaqr_set_values(self.h, vals_dev)
 
     def cgls(self, b_dev, tol=1e-10, max_iter=200):
@@ -262,6 +283,16 @@ class Solver:
         x = torch.empty(self.N, dtype=torch.float64, device=b_dev.device)
         info = spaqr_cgls(self.h, b_dev, x, tol, max_iter)
         return x, info
+
+    def adjoint(self, x_dev, b_dev, g_dev, tol=1e-12, max_iter=500):
+        """(grad_b, grad_vals, lambda, info) of the least-squares solution x."""
+        import torch
+        dev = g_dev.device
+        gb = torch.empty(self.M, dtype=torch.float64, device=dev)
+        gv = torch.empty(self.nnz, dtype=torch.float64, device=dev)
+        lam = torch.empty(self.N, dtype=torch.float64, device=dev)
+        info = spaqr_adjoint(self.h, x_dev, b_dev, g_dev, gb, gv, lam, tol, max_iter)
+        return gb, gv, lam, info
 
     def apply(self, b_dev):
         import torch
