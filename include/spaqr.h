@@ -154,6 +154,34 @@ int spaqr_apply_op(spaqr_handle h, int32_t op, const double* in_dev, double* out
 int spaqr_cgls(spaqr_handle h, const double* b_dev, double tol, int32_t max_iter, double* x_dev,
                spaqr_cgls_info* info);
 
+/* Batch of independent problems in one handle.  Each member is analysed
+ * as by spaqr_analyze (arrays of count pointers / sizes / options); the
+ * handle then holds their block-diagonal union: member g owns columns
+ * [col_off[g], col_off[g+1]) and rows [row_off[g], row_off[g+1]) of the
+ * batch vectors.  Tree levels are aligned from the leaves, so
+ * spaqr_factorize on the handle eliminates, scales and sparsifies the
+ * same-level clusters of every member in the same launches (Algorithm 1
+ * run on all members at once; each member's factor equals its own).
+ * Members must share precision, device, stream, sparsify_skip and
+ * sep_width (SPAQR_EARG otherwise, naming the member).  spaqr_apply and
+ * spaqr_apply_op act on the batch vectors; spaqr_cgls runs every member's
+ * CGLS independently and reports the worst member; spaqr_adjoint needs a
+ * single-problem handle. */
+int spaqr_batch_analyze(int32_t count, const int64_t* const* row_ptr, const int32_t* const* col_idx,
+                        const double* const* vals, const int64_t* M, const int64_t* N,
+                        const spaqr_options* opts, spaqr_handle* out);
+
+/* Member count and offsets (host buffers of count + 1, either may be NULL). */
+int spaqr_batch_info(spaqr_handle h, int32_t* count, int64_t* col_off, int64_t* row_off);
+
+/* CGLS of every member at once, each with its own recurrence scalars and
+ * stopping test (Section 4); a member that has converged is frozen while
+ * the others go on.  b_dev: total-M doubles, x_dev: total-N doubles (batch
+ * order); infos: count entries (may be NULL).  SPAQR_NOCONV if a member
+ * reached max_iter. */
+int spaqr_batch_cgls(spaqr_handle h, const double* b_dev, double tol, int32_t max_iter, double* x_dev,
+                     spaqr_cgls_info* infos);
+
 /* Adjoint of the least-squares solution x = argmin ||A x - b|| for a loss
  * with gradient g = dL/dx: solves A^T A lambda = g by conjugate gradients
  * preconditioned with the factor of the current values, M^-1 =

@@ -45,19 +45,6 @@ __global__ void k_colscale(const int64_t* __restrict__ at_ptr, const int64_t* __
   }
 }
 
-__global__ void k_fill(double* __restrict__ d, double v, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (i < n) d[i] = v;
-}
-
-// d = s / sqrt(sc[slot])
-__global__ void k_normalize(double* __restrict__ d, const double* __restrict__ s, int64_t n,
-                            const double* __restrict__ sc, int slot) {
-  const double f = 1.0 / sqrt(sc[slot]);
-  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (i < n) d[i] = s[i] * f;
-}
-
 // One thread per row i: g[e] = r_i lam_j - al_i x_j for the entries e of row i.
 __global__ void k_adj_grad(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                            const double* __restrict__ r, const double* __restrict__ al,
@@ -78,18 +65,6 @@ void launch_colscale(const int64_t* at_ptr, const int64_t* at_src, const double*
                      double* D, double* ahat, double* ahatT, int* bad, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_colscale, dim3(nb(n)), dim3(BS), 0, s, at_ptr, at_src, vals, n, D, ahat, ahatT, bad);
-  SPAQR_HIP(hipGetLastError());
-}
-
-void launch_fill(double* d, double v, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_fill, dim3(nb(n)), dim3(BS), 0, s, d, v, n);
-  SPAQR_HIP(hipGetLastError());
-}
-
-void launch_normalize(double* d, const double* src, int64_t n, const double* sc, int slot, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_normalize, dim3(nb(n)), dim3(BS), 0, s, d, src, n, sc, slot);
   SPAQR_HIP(hipGetLastError());
 }
 

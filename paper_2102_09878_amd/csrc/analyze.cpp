@@ -379,6 +379,10 @@ void analyze_plan(Plan& P, const int64_t* row_ptr, const int32_t* col_idx, const
       P.init_dst[e] = g.offset + row_pos[r] + (int64_t)col * g.ld;
     }
   }
+  P.count = 1;
+  P.seg_col = {0, N};
+  P.seg_row = {0, M};
+  P.seg_depth = {P.depth};
   // A^T pattern
   P.at_ptr.assign(N + 1, 0);
   for (int64_t e = 0; e < P.nnz; ++e) P.at_ptr[col_idx[e] + 1]++;
@@ -392,6 +396,80 @@ void analyze_plan(Plan& P, const int64_t* row_ptr, const int32_t* col_idx, const
       P.at_idx[d] = (int32_t)r;
       P.at_src[d] = e;
     }
+}
+
+void union_plans(Plan& U, std::vector<Plan>& parts) {
+  if (parts.empty()) throw Error(SPAQR_EARG, "empty batch");
+  U = Plan();
+  int dmax = 0;
+  for (const Plan& p : parts) {
+    dmax = std::max(dmax, p.depth);
+    if (p.skip != parts[0].skip) throw Error(SPAQR_EARG, "batch members must share sparsify_skip");
+    if (p.w != parts[0].w) throw Error(SPAQR_EARG, "batch members must share sep_width");
+  }
+  U.depth = dmax;
+  U.skip = parts[0].skip;
+  U.w = parts[0].w;
+  U.count = (int)parts.size();
+  U.seg_col = {0};
+  U.seg_row = {0};
+  int64_t nnz = 0, elems = 0;
+  for (const Plan& p : parts) {
+    const int shift = dmax - p.depth;
+    const int nb = (int)U.nodes.size(), cb = (int)U.clusters.size(), fb = (int)U.finest.size();
+    const int64_t colb = U.N, rowb = U.M, nzb = nnz, eb = elems;
+    for (NDNode n : p.nodes) {
+      n.level += shift;
+      n.rank += nb;
+      for (int& c : n.child)
+        if (c >= 0) c += nb;
+      if (n.parent >= 0) n.parent += nb;
+      for (auto& lst : n.pieces)
+        for (int& c : lst) c += cb;
+      U.nodes.push_back(std::move(n));
+    }
+    for (Cluster c : p.clusters) {
+      c.sep += nb;
+      c.gran += shift;
+      if (c.parent >= 0) c.parent += cb;
+      for (int& k : c.children) k += cb;
+      for (int& j : c.cells) j += (int)colb;
+      if (c.finest_index >= 0) c.finest_index += fb;
+      U.clusters.push_back(std::move(c));
+    }
+    for (int f : p.finest) U.finest.push_back(f + cb);
+    for (int c : p.col_cluster) U.col_cluster.push_back(c + cb);
+    for (int c : p.row_owner) U.row_owner.push_back(c + cb);
+    for (InitGroup g : p.init_groups) {
+      g.owner += cb;
+      for (int& r : g.rows) r += (int)rowb;
+      for (int& c : g.clus) c += cb;
+      g.offset += eb;
+      U.init_groups.push_back(std::move(g));
+    }
+    for (int64_t d : p.init_dst) U.init_dst.push_back(d + eb);
+    for (int64_t r = 0; r < p.M; ++r) U.row_ptr.push_back(p.row_ptr[r] + nzb);
+    for (int32_t c : p.col_idx) U.col_idx.push_back(c + (int32_t)colb);
+    U.vals.insert(U.vals.end(), p.vals.begin(), p.vals.end());
+    U.ahat.insert(U.ahat.end(), p.ahat.begin(), p.ahat.end());
+    U.D.insert(U.D.end(), p.D.begin(), p.D.end());
+    for (int64_t j = 0; j < p.N; ++j) U.at_ptr.push_back(p.at_ptr[j] + nzb);
+    for (int32_t r : p.at_idx) U.at_idx.push_back(r + (int32_t)rowb);
+    for (int64_t e : p.at_src) U.at_src.push_back(e + nzb);
+    U.M += p.M;
+    U.N += p.N;
+    nnz += p.nnz;
+    elems += (p.init_elems + 63) / 64 * 64;
+    U.seg_col.push_back(U.N);
+    U.seg_row.push_back(U.M);
+    U.seg_depth.push_back(p.depth);
+  }
+  if (U.N >= (int64_t)1 << 31 || U.M >= (int64_t)1 << 31) throw Error(SPAQR_EARG, "batch too large");
+  U.row_ptr.push_back(nnz);
+  U.at_ptr.push_back(nnz);
+  U.nnz = nnz;
+  U.init_elems = elems;
+  U.grid[0] = U.grid[1] = U.grid[2] = 0;  // no single grid
 }
 
 }  // namespace spaqr

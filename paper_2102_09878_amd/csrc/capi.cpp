@@ -1,10 +1,12 @@
 // extern "C" boundary of libspaqr: argument checks, error capture, and
 // dispatch into the host analysis, the device factorization and the
 // solvers.  No C++ exception leaves this file.
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "handle.h"
 
@@ -126,7 +128,72 @@ int spaqr_cgls(spaqr_handle h, const double* b_dev, double tol, int32_t max_iter
                spaqr_cgls_info* info) {
   return guard(h, [&]() -> int {
     if (!h || !b_dev || !x_dev) throw spaqr::Error(SPAQR_EARG, "null argument");
-    return spaqr::cgls(h->h, b_dev, tol, max_iter, x_dev, info);
+    std::vector<spaqr_cgls_info> all(h->h.P.count);
+    const int rc = spaqr::cgls(h->h, b_dev, tol, max_iter, x_dev, all.data());
+    if (info) {
+      // a batch reports its worst member
+      spaqr_cgls_info w = all[0];
+      for (const auto& a : all) {
+        w.iters = std::max(w.iters, a.iters);
+        w.converged = w.converged && a.converged;
+        w.residual = std::max(w.residual, a.residual);
+        w.paper_residual = std::max(w.paper_residual, a.paper_residual);
+        w.norm_a = std::max(w.norm_a, a.norm_a);
+      }
+      *info = w;
+    }
+    return rc;
+  });
+}
+
+int spaqr_batch_analyze(int32_t count, const int64_t* const* row_ptr, const int32_t* const* col_idx,
+                        const double* const* vals, const int64_t* M, const int64_t* N, const spaqr_options* opts,
+                        spaqr_handle* out) {
+  return guard(nullptr, [&]() -> int {
+    if (!out || !opts || !row_ptr || !col_idx || !vals || !M || !N || count < 1)
+      throw spaqr::Error(SPAQR_EARG, "bad argument");
+    *out = nullptr;
+    for (int32_t g = 0; g < count; ++g) {
+      const spaqr_options& o = opts[g];
+      if (o.precision != opts[0].precision || o.device != opts[0].device || o.stream != opts[0].stream)
+        throw spaqr::Error(SPAQR_EARG, "batch members must share precision, device and stream");
+      if (o.precision != SPAQR_FP64 && o.precision != SPAQR_FP32_FACTOR)
+        throw spaqr::Error(SPAQR_EARG, "unknown precision");
+    }
+    std::vector<spaqr::Plan> parts(count);
+    for (int32_t g = 0; g < count; ++g) {
+      try {
+        spaqr::analyze_plan(parts[g], row_ptr[g], col_idx[g], vals[g], M[g], N[g], opts[g]);
+      } catch (const spaqr::Error& e) {
+        throw spaqr::Error(e.code, "batch member " + std::to_string(g) + ": " + e.what());
+      }
+    }
+    std::unique_ptr<spaqr_handle_s> h(new spaqr_handle_s());
+    h->h.opt = opts[0];
+    spaqr::union_plans(h->h.P, parts);
+    *out = h.release();
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_batch_info(spaqr_handle h, int32_t* count, int64_t* col_off, int64_t* row_off) {
+  return guard(h, [&]() -> int {
+    if (!h || !count) throw spaqr::Error(SPAQR_EARG, "null argument");
+    const spaqr::Plan& P = h->h.P;
+    *count = P.count;
+    for (int g = 0; g <= P.count; ++g) {
+      if (col_off) col_off[g] = P.seg_col[g];
+      if (row_off) row_off[g] = P.seg_row[g];
+    }
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_batch_cgls(spaqr_handle h, const double* b_dev, double tol, int32_t max_iter, double* x_dev,
+                     spaqr_cgls_info* infos) {
+  return guard(h, [&]() -> int {
+    if (!h || !b_dev || !x_dev) throw spaqr::Error(SPAQR_EARG, "null argument");
+    return spaqr::cgls(h->h, b_dev, tol, max_iter, x_dev, infos);
   });
 }
 

@@ -104,9 +104,15 @@ void Handle::release_device() {
   if (!dev_ready) return;
   (void)hipStreamSynchronize(stream);
   for (void* p : {(void*)d_ahat, (void*)d_rp, (void*)d_ci, (void*)d_ahatT, (void*)d_atp, (void*)d_ati,
-                  (void*)d_init_dst, (void*)d_D, (void*)d_cg, (void*)d_vals, (void*)d_atsrc, (void*)d_flag})
+                  (void*)d_init_dst, (void*)d_D, (void*)d_cg, (void*)d_vals, (void*)d_atsrc, (void*)d_flag,
+                  (void*)d_segc, (void*)d_segr, (void*)d_act})
     if (p) (void)hipFree(p);
   if (h_sc) (void)hipHostFree(h_sc);
+  if (h_act) (void)hipHostFree(h_act);
+  d_segc = d_segr = nullptr;
+  d_act = nullptr;
+  h_act = nullptr;
+  cg_elems = 0;
   d_ahat = d_ahatT = d_D = d_cg = d_vals = nullptr;
   d_atsrc = nullptr;
   d_flag = nullptr;
@@ -147,7 +153,11 @@ void Handle::ensure_device() {
   d_ahatT = dcopy(std::vector<double>(P.nnz), plan_bytes);
   d_D = dcopy(std::vector<double>(P.N), plan_bytes);
   d_flag = dcopy(std::vector<int>(1), plan_bytes);
-  SPAQR_HIP(hipHostMalloc((void**)&h_sc, 64 * sizeof(double), hipHostMallocDefault));
+  d_segc = dcopy(P.seg_col, plan_bytes);
+  d_segr = dcopy(P.seg_row, plan_bytes);
+  d_act = dcopy(std::vector<int>(P.count, 1), plan_bytes);
+  SPAQR_HIP(hipHostMalloc((void**)&h_sc, (P.count * 8 + 64) * sizeof(double), hipHostMallocDefault));
+  SPAQR_HIP(hipHostMalloc((void**)&h_act, P.count * sizeof(int), hipHostMallocDefault));
   dev_ready = true;
   scale_values(*this);
 }
@@ -285,6 +295,14 @@ class Factorizer {
   void timer_end() { SPAQR_HIP(hipEventRecord(timers_.back().second.second, st)); }
 
   void kill_group(int g) { G[g].alive = false; }
+
+  // touch[c]: groups whose cluster list has held c (may be stale; checked
+  // on use).  Kept so an interface can be removed from every group that
+  // touches it without scanning all groups.
+  std::vector<std::vector<int>> touch;
+  void note(int g) {
+    for (int c : G[g].clus) touch[c].push_back(g);
+  }
 
   std::vector<int> live_groups() {
     std::vector<int> out;
@@ -466,6 +484,7 @@ template <typename T>
 void Factorizer<T>::init_groups() {
   const size_t nc = P.clusters.size();
   C.assign(nc, RC());
+  touch.assign(nc, {});
   pos.assign(P.N, -1);
   T* base = talloc(P.init_elems);
   SPAQR_HIP(hipMemsetAsync(base, 0, std::max<int64_t>(1, P.init_elems) * sizeof(T), st));
@@ -481,6 +500,7 @@ void Factorizer<T>::init_groups() {
     g.clus = ig.clus;
     C[ig.owner].groups.push_back((int)G.size());
     G.push_back(std::move(g));
+    note((int)G.size() - 1);
   }
   for (int f : P.finest) {
     C[f].slots = P.clusters[f].cells;
@@ -503,35 +523,48 @@ void Factorizer<T>::eliminate_level(int m) {
     H.stats.top_cols = (int)C[s].slots.size();
     H.stats.top_rows = rows;
   }
+  std::vector<int> idx(P.clusters.size(), -1), mark(P.clusters.size(), 0);
   while (!pending.empty()) {
-    // neighbours of every pending cluster from the current structure
+    // neighbours of every pending cluster from the current structure: the
+    // clusters touched by any live group that s owns or that touches s
+    for (size_t i = 0; i < pending.size(); ++i) idx[pending[i]] = (int)i;
     std::vector<std::vector<int>> nb(pending.size());
-    for (size_t i = 0; i < pending.size(); ++i) {
-      const int s = pending[i];
-      std::vector<int> u;
-      for (int g : C[s].groups) u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
-      for (int c : live) {
-        if (c == s) continue;
-        for (int g : C[c].groups)
-          if (has(G[g].clus, s)) u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
+    for (int c : live)
+      for (int g : C[c].groups) {
+        const RG& gr = G[g];
+        auto add = [&](int s) {
+          if (idx[s] >= 0) nb[idx[s]].insert(nb[idx[s]].end(), gr.clus.begin(), gr.clus.end());
+        };
+        add(c);
+        for (int q : gr.clus)
+          if (q != c) add(q);
       }
+    for (size_t i = 0; i < pending.size(); ++i) {
+      auto& u = nb[i];
       std::sort(u.begin(), u.end());
       u.erase(std::unique(u.begin(), u.end()), u.end());
-      u.erase(std::remove(u.begin(), u.end(), s), u.end());
-      nb[i] = std::move(u);
+      u.erase(std::remove(u.begin(), u.end(), pending[i]), u.end());
     }
+    // greedy round in id order: s joins unless a cluster already taken is
+    // its neighbour or has it as a neighbour (mark[] holds both relations)
     std::vector<int> sel, rest;
-    std::vector<size_t> seli;
     for (size_t i = 0; i < pending.size(); ++i) {
-      bool ok = true;
-      for (size_t j : seli)
-        if (has(nb[i], pending[j]) || has(nb[j], pending[i])) ok = false;
+      const int s = pending[i];
+      bool ok = !mark[s];
+      for (int q : nb[i]) ok = ok && mark[q] != 2;
       if (ok) {
-        sel.push_back(pending[i]);
-        seli.push_back(i);
+        sel.push_back(s);
+        mark[s] = 2;
+        for (int q : nb[i])
+          if (!mark[q]) mark[q] = 1;
       } else {
-        rest.push_back(pending[i]);
+        rest.push_back(s);
       }
+    }
+    for (size_t i = 0; i < pending.size(); ++i) {
+      idx[pending[i]] = -1;
+      mark[pending[i]] = 0;
+      for (int q : nb[i]) mark[q] = 0;
     }
     eliminate_round(sel);
     pending.swap(rest);
@@ -555,20 +588,23 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
   std::vector<QRDesc> qd;
   int maxc = 0;
   timer_begin(PH_ELIM);
+  // foreign rows of every front in one pass over the live groups (by owner
+  // id, then group order): groups of other owners that touch the front
+  {
+    std::vector<int> fidx(P.clusters.size(), -1);
+    for (size_t i = 0; i < sel.size(); ++i) fidx[sel[i]] = (int)i;
+    for (int c : live)
+      for (int g : C[c].groups)
+        for (int q : G[g].clus)
+          if (q != c && fidx[q] >= 0) fr[fidx[q]].foreign.push_back(g);
+  }
   for (size_t i = 0; i < sel.size(); ++i) {
     Front& f = fr[i];
     f.s = sel[i];
     f.owned = C[f.s].groups;
     std::vector<int> u;
     for (int g : f.owned) u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
-    for (int c : live) {
-      if (c == f.s) continue;
-      for (int g : C[c].groups)
-        if (has(G[g].clus, f.s)) {
-          f.foreign.push_back(g);
-          u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
-        }
-    }
+    for (int g : f.foreign) u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
     std::sort(u.begin(), u.end());
     u.erase(std::unique(u.begin(), u.end()), u.end());
     u.erase(std::remove(u.begin(), u.end(), f.s), u.end());
@@ -638,6 +674,7 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
       gr.slots = s2;
       gr.clus = f.nb;
       gr.role = 0;
+      note(g);
       off += gr.nrows;
     }
     if (f.cN > 0 && f.rs > f.cs) {
@@ -746,6 +783,7 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
       maxcols = std::max(maxcols, f.cN);
       C[g.owner].groups.push_back((int)G.size());
       G.push_back(std::move(g));
+      note((int)G.size() - 1);
     }
   }
   int* drp = upload(rp.v);
@@ -855,6 +893,7 @@ void Factorizer<T>::scale_all() {
     p1.role = 1;
     C[f.p].groups.push_back((int)G.size());
     G.push_back(std::move(p1));
+    note((int)G.size() - 1);
     if (f.m > f.cs && f.n > f.cs) {
       RG p2;
       p2.owner = f.p;
@@ -866,6 +905,7 @@ void Factorizer<T>::scale_all() {
       p2.role = 2;
       C[f.p].groups.push_back((int)G.size());
       G.push_back(std::move(p2));
+      note((int)G.size() - 1);
     }
   }
   // right scaling of every column block by R_qq^-1
@@ -973,16 +1013,23 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
   std::vector<size_t> sd_map;
   int* d_rank = static_cast<int*>(H.arena.alloc(std::max<size_t>(1, sel.size()) * sizeof(int)));
   int maxc = 0;
-  const std::vector<int> lg = live_groups();
+  // every live group touching p, except p's scaled rows, in live-group order
+  {
+    std::vector<int> sidx(P.clusters.size(), -1);
+    for (size_t i = 0; i < sel.size(); ++i) {
+      sidx[sel[i]] = (int)i;
+      ss[i].p1 = -1;
+      for (int g : C[sel[i]].groups)
+        if (G[g].role == 1) ss[i].p1 = g;
+      if (ss[i].p1 < 0) throw Error(SPAQR_EARG, "internal: interface without scaled rows");
+    }
+    for (int g : live_groups())
+      for (int q : G[g].clus)
+        if (sidx[q] >= 0 && g != ss[sidx[q]].p1) ss[sidx[q]].blocks.push_back(g);
+  }
   for (size_t i = 0; i < sel.size(); ++i) {
     S2& s = ss[i];
     s.p = sel[i];
-    s.p1 = -1;
-    for (int g : C[s.p].groups)
-      if (G[g].role == 1) s.p1 = g;
-    if (s.p1 < 0) throw Error(SPAQR_EARG, "internal: interface without scaled rows");
-    for (int g : lg)
-      if (g != s.p1 && has(G[g].clus, s.p)) s.blocks.push_back(g);
     for (int c : G[s.p1].clus)
       if (c != s.p) s.others.push_back(c);
     s.oslots = slots_of(s.others);
@@ -1104,11 +1151,12 @@ template <typename T>
 void Factorizer<T>::vanish(int p) {
   C[p].alive = false;
   live.erase(p);
-  for (int g : live_groups()) {
+  for (int g : touch[p]) {
     auto& cl = G[g].clus;
     auto it = std::lower_bound(cl.begin(), cl.end(), p);
     if (it != cl.end() && *it == p) cl.erase(it);
   }
+  touch[p].clear();
   std::vector<int> mine = C[p].groups;
   C[p].groups.clear();
   for (int g : mine) {
@@ -1174,6 +1222,7 @@ void Factorizer<T>::reassign_group_rows(int gi) {
     rd.push_back(c);
     C[g.owner].groups.push_back((int)G.size());
     G.push_back(std::move(g));
+    note((int)G.size() - 1);
   }
   int* drp = upload(rp.v);
   for (size_t i = 0; i < rd.size(); ++i) rd[i].rows = drp + rmap[i];
@@ -1216,10 +1265,13 @@ void Factorizer<T>::merge(int m) {
   if (!any) return;
   for (int g : live_groups()) {
     auto& cl = G[g].clus;
+    bool hit = false;
     for (int& c : cl)
-      if (remap[c] >= 0) c = remap[c];
+      if (remap[c] >= 0) c = remap[c], hit = true;
+    if (!hit) continue;
     std::sort(cl.begin(), cl.end());
     cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
+    note(g);
   }
 }
 
@@ -1317,6 +1369,7 @@ void Factorizer<T>::run() {
       scale_all();
       step1_all();
       std::vector<int> pending(live.begin(), live.end());
+      std::vector<char> taken(P.clusters.size(), 0), blocked(P.clusters.size(), 0);
       round_ = 0;
       while (!pending.empty()) {
         auto p1 = [&](int p) {
@@ -1324,12 +1377,24 @@ void Factorizer<T>::run() {
             if (G[g].role == 1) return g;
           throw Error(SPAQR_EARG, "internal: interface without scaled rows");
         };
+        // p joins unless a taken q lies among the columns of p's scaled
+        // rows (taken[q]) or p among q's (blocked[p])
         std::vector<int> sel, rest;
         for (int p : pending) {
-          bool ok = true;
-          for (int q : sel)
-            if (has(G[p1(p)].clus, q) || has(G[p1(q)].clus, p)) ok = false;
-          (ok ? sel : rest).push_back(p);
+          const auto& cl = G[p1(p)].clus;
+          bool ok = !blocked[p];
+          for (int q : cl) ok = ok && !taken[q];
+          if (ok) {
+            sel.push_back(p);
+            taken[p] = 1;
+            for (int q : cl) blocked[q] = 1;
+          } else {
+            rest.push_back(p);
+          }
+        }
+        for (int p : sel) {
+          taken[p] = 0;
+          for (int q : G[p1(p)].clus) blocked[q] = 0;
         }
         step2_round(sel);
         pending.swap(rest);

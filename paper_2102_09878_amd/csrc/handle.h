@@ -98,7 +98,10 @@ struct Handle {
   double* d_vals = nullptr;     // values of A as given (CSR order)
   int64_t* d_atsrc = nullptr;   // CSR entry of each transposed entry
   int* d_flag = nullptr;
-  double normA = 0.0;           // ||A||_2 estimate of the current values
+  int64_t* d_segc = nullptr;    // problem offsets over columns / rows (count + 1)
+  int64_t* d_segr = nullptr;
+  int* d_act = nullptr;         // per-problem "still iterating" flags
+  std::vector<double> normA;    // ||A_g||_2 estimate of each problem's current values
   size_t plan_bytes = 0;
   // factor
   Arena arena;
@@ -114,7 +117,8 @@ struct Handle {
   // solver workspace
   double* d_cg = nullptr;
   size_t cg_elems = 0;
-  double* h_sc = nullptr;  // pinned scalars
+  double* h_sc = nullptr;  // pinned scalars (count * 8 + 64 doubles)
+  int* h_act = nullptr;    // pinned flags (count ints)
 
   ~Handle();
   void ensure_device();
@@ -123,7 +127,10 @@ struct Handle {
 
 void factorize(Handle& H, double eps, const int* forced, int nforced);
 void apply_op(Handle& H, bool transpose, double* x_dev);
-int cgls(Handle& H, const double* b, double tol, int max_iter, double* x, spaqr_cgls_info* info);
+// CGLS on every problem of the plan at once, each with its own scalars and
+// stopping test; infos[count] (may be null).  Returns SPAQR_NOCONV if any
+// problem reached max_iter.
+int cgls(Handle& H, const double* b, double tol, int max_iter, double* x, spaqr_cgls_info* infos);
 void csne(Handle& H, const double* b, double* x);
 // Column scaling of the current device values d_vals: D, Ahat, Ahat^T and
 // the ||A||_2 estimate, all on the device.

@@ -2,8 +2,14 @@
 // (Section 4), the one-shot seminormal solve (Section 1) and the adjoint
 // solve A^T A lambda = g preconditioned by the same factor; plus the column
 // scaling that precedes everything (Algorithm 1).  All vector work runs in
-// device kernels; the host only reads one residual norm per iteration to
-// decide whether to stop.
+// device kernels; the host reads one vector of residual norms per
+// iteration to decide which problems go on.
+//
+// A plan may hold a batch of independent problems (block-diagonal union):
+// products with A and the W sweeps act on all of them in one launch each,
+// while every scalar of the recurrences and every stopping test is per
+// problem.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -24,8 +30,8 @@ struct Vecs {
 };
 
 Vecs workspace(Handle& H) {
-  const size_t N = H.P.N, M = H.P.M;
-  const size_t need = 5 * N + 2 * M + 1024 + SC_N;
+  const size_t N = H.P.N, M = H.P.M, G = H.P.count;
+  const size_t need = 5 * N + 2 * M + G * SDOT_MAX_BLOCKS + G * SC_N;
   if (H.cg_elems < need) {
     if (H.d_cg) SPAQR_HIP(hipFree(H.d_cg));
     H.d_cg = nullptr;
@@ -43,9 +49,17 @@ Vecs workspace(Handle& H) {
   v.r = b + 5 * N;
   v.q = b + 5 * N + M;
   v.part = b + 5 * N + 2 * M;
-  v.sc = v.part + 1024;
+  v.sc = v.part + G * SDOT_MAX_BLOCKS;
   return v;
 }
+
+int64_t longest(const std::vector<int64_t>& seg) {
+  int64_t m = 0;
+  for (size_t g = 0; g + 1 < seg.size(); ++g) m = std::max(m, seg[g + 1] - seg[g]);
+  return m;
+}
+Segs cols(Handle& H) { return Segs{H.d_segc, H.P.count, longest(H.P.seg_col)}; }
+Segs rows(Handle& H) { return Segs{H.d_segr, H.P.count, longest(H.P.seg_row)}; }
 
 // t = Ahat^T r  (Ahat = A D^-1)
 void atmul(Handle& H, const double* r, double* t) {
@@ -56,13 +70,53 @@ void amul(Handle& H, const double* u, double* q) {
   launch_spmv(H.d_rp, H.d_ci, H.d_ahat, u, q, H.P.M, H.stream);
 }
 
-double read_scalar(Handle& H, const double* d) {
-  SPAQR_HIP(hipMemcpyAsync(H.h_sc, d, sizeof(double), hipMemcpyDeviceToHost, H.stream));
+// one slot of every problem's scalars, to the host
+void read_slot(Handle& H, const double* sc, int slot, std::vector<double>& out) {
+  const int G = H.P.count;
+  SPAQR_HIP(hipMemcpyAsync(H.h_sc, sc, (size_t)G * SC_N * sizeof(double), hipMemcpyDeviceToHost, H.stream));
   SPAQR_HIP(hipStreamSynchronize(H.stream));
-  return H.h_sc[0];
+  out.resize(G);
+  for (int g = 0; g < G; ++g) out[g] = H.h_sc[(size_t)g * SC_N + slot];
+}
+
+void upload_act(Handle& H, const std::vector<int>& act) {
+  std::memcpy(H.h_act, act.data(), act.size() * sizeof(int));
+  SPAQR_HIP(hipMemcpyAsync(H.d_act, H.h_act, act.size() * sizeof(int), hipMemcpyHostToDevice, H.stream));
 }
 
 }  // namespace
+
+void scale_values(Handle& H) {
+  Vecs v = workspace(H);
+  const int64_t N = H.P.N;
+  hipStream_t st = H.stream;
+  SPAQR_HIP(hipMemsetAsync(H.d_flag, 0, sizeof(int), st));
+  launch_colscale(H.d_atp, H.d_atsrc, H.d_vals, N, H.d_D, H.d_ahat, H.d_ahatT, H.d_flag, st);
+  int bad = 0;
+  SPAQR_HIP(hipMemcpyAsync(H.h_act, H.d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  SPAQR_HIP(hipStreamSynchronize(st));
+  bad = H.h_act[0];
+  if (bad) throw Error(SPAQR_EARG, "a column of A has zero norm");
+  // ||A_g||_2: 30 power steps on A^T A = D Ahat^T Ahat D from the all-ones
+  // vector of each problem (a lower bound of the norm)
+  const Segs sc = cols(H);
+  for (int g = 0; g < H.P.count; ++g) {
+    const int64_t lo = H.P.seg_col[g], hi = H.P.seg_col[g + 1];
+    launch_fill(v.p + lo, 1.0 / std::sqrt((double)(hi - lo)), hi - lo, st);
+  }
+  for (int it = 0; it < 30; ++it) {
+    launch_scale(v.u, v.p, H.d_D, N, true, st);
+    amul(H, v.u, v.q);
+    atmul(H, v.q, v.t);
+    launch_scale(v.t, v.t, H.d_D, N, true, st);
+    launch_sdot(v.t, nullptr, nullptr, sc, v.part, v.sc, SC_PW, st);
+    launch_normalize(v.p, v.t, sc, v.sc, SC_PW, st);
+  }
+  std::vector<double> lam2;
+  read_slot(H, v.sc, SC_PW, lam2);
+  H.normA.assign(H.P.count, 0.0);
+  for (int g = 0; g < H.P.count; ++g) H.normA[g] = std::sqrt(std::sqrt(lam2[g]));
+}
 
 void csne(Handle& H, const double* b, double* x) {
   if (!H.factored) throw Error(SPAQR_ESTATE, "factorize first");
@@ -76,135 +130,142 @@ void csne(Handle& H, const double* b, double* x) {
   H.kt.harvest();
 }
 
-int cgls(Handle& H, const double* b, double tol, int max_iter, double* x, spaqr_cgls_info* info) {
+int cgls(Handle& H, const double* b, double tol, int max_iter, double* x, spaqr_cgls_info* infos) {
   if (!H.factored) throw Error(SPAQR_ESTATE, "factorize first");
   if (!(tol >= 0.0) || max_iter < 0) throw Error(SPAQR_EARG, "bad tolerance or iteration limit");
   const double t0 = now_s();
   Vecs v = workspace(H);
   const int64_t N = H.P.N, M = H.P.M;
+  const int G = H.P.count;
+  const Segs sc = cols(H), sr = rows(H);
   hipStream_t st = H.stream;
   // r = b, t = Ahat^T r, ||A^T b|| = ||D t||
   launch_copy(v.r, b, M, st);
   atmul(H, v.r, v.t);
-  launch_dot(v.t, nullptr, H.d_D, N, v.part, v.sc + SC_ATB, st);
-  launch_dot(b, nullptr, nullptr, M, v.part, v.sc + SC_TRUE, st);
+  launch_sdot(v.t, nullptr, H.d_D, sc, v.part, v.sc, SC_ATB, st);
+  launch_sdot(b, nullptr, nullptr, sr, v.part, v.sc, SC_TRUE, st);
   // s = W^-T t, p = s, gamma = ||s||^2, y = 0
   launch_copy(v.s, v.t, N, st);
   apply_op(H, true, v.s);
   launch_copy(v.p, v.s, N, st);
-  launch_dot(v.s, nullptr, nullptr, N, v.part, v.sc + SC_G, st);
+  launch_sdot(v.s, nullptr, nullptr, sc, v.part, v.sc, SC_G, st);
   SPAQR_HIP(hipMemsetAsync(v.y, 0, N * sizeof(double), st));
-  SPAQR_HIP(hipMemcpyAsync(H.h_sc, v.sc, SC_N * sizeof(double), hipMemcpyDeviceToHost, st));
-  SPAQR_HIP(hipStreamSynchronize(st));
-  const double atb = std::sqrt(H.h_sc[SC_ATB]);
-  const double nb = std::sqrt(H.h_sc[SC_TRUE]);
-  const double normA = H.normA;
-  const double denom = normA * nb;
-  double res = denom > 0 ? atb / denom : 0.0;
+  std::vector<double> atb2, b2;
+  read_slot(H, v.sc, SC_ATB, atb2);
+  for (int g = 0; g < G; ++g) b2.push_back(H.h_sc[(size_t)g * SC_N + SC_TRUE]);
+  std::vector<double> denom(G), res(G), atb(G);
+  std::vector<int> act(G), iters(G, 0);
+  int nact = 0;
+  for (int g = 0; g < G; ++g) {
+    atb[g] = std::sqrt(atb2[g]);
+    denom[g] = H.normA[g] * std::sqrt(b2[g]);
+    res[g] = denom[g] > 0 ? atb[g] / denom[g] : 0.0;
+    act[g] = res[g] > tol ? 1 : 0;
+    nact += act[g];
+  }
+  upload_act(H, act);
   int it = 0;
-  while (res > tol && it < max_iter) {
+  std::vector<double> tt;
+  while (nact > 0 && it < max_iter) {
     // q = Ahat W^-1 p
     launch_copy(v.u, v.p, N, st);
     apply_op(H, false, v.u);
     amul(H, v.u, v.q);
-    launch_dot(v.q, nullptr, nullptr, M, v.part, v.sc + SC_QQ, st);
-    launch_step(v.y, v.p, N, v.r, v.q, M, v.sc, st);
+    launch_sdot(v.q, nullptr, nullptr, sr, v.part, v.sc, SC_QQ, st);
+    launch_step(v.y, v.p, sc, v.r, v.q, sr, H.d_act, v.sc, st);
     // t = Ahat^T r, ||A^T r|| = ||D t||
     atmul(H, v.r, v.t);
-    launch_dot(v.t, nullptr, H.d_D, N, v.part, v.sc + SC_TT, st);
+    launch_sdot(v.t, nullptr, H.d_D, sc, v.part, v.sc, SC_TT, st);
     // s = W^-T t, p = s + beta p
     launch_copy(v.s, v.t, N, st);
     apply_op(H, true, v.s);
-    launch_dot(v.s, nullptr, nullptr, N, v.part, v.sc + SC_GN, st);
-    launch_pupdate(v.p, v.s, N, v.sc, st);
-    launch_set(v.sc, SC_G, SC_GN, st);
+    launch_sdot(v.s, nullptr, nullptr, sc, v.part, v.sc, SC_GN, st);
+    launch_pupdate(v.p, v.s, sc, H.d_act, v.sc, st);
+    launch_set(v.sc, SC_G, SC_GN, H.d_act, G, st);
     ++it;
-    res = std::sqrt(read_scalar(H, v.sc + SC_TT)) / denom;
+    read_slot(H, v.sc, SC_TT, tt);
+    nact = 0;
+    for (int g = 0; g < G; ++g) {
+      if (!act[g]) continue;
+      ++iters[g];
+      res[g] = std::sqrt(tt[g]) / denom[g];
+      act[g] = res[g] > tol ? 1 : 0;
+      nact += act[g];
+    }
+    if (nact > 0) upload_act(H, act);
   }
-  // x = D^-1 W^-1 y and the true residual in FP64
+  // x = D^-1 W^-1 y and the true residuals in FP64
   launch_copy(v.u, v.y, N, st);
   apply_op(H, false, v.u);
   launch_scale(x, v.u, H.d_D, N, false, st);
   amul(H, v.u, v.q);
   launch_sub(v.r, b, v.q, M, st);
   atmul(H, v.r, v.t);
-  launch_dot(v.t, nullptr, H.d_D, N, v.part, v.sc + SC_TT, st);
-  const double tt = std::sqrt(read_scalar(H, v.sc + SC_TT));
+  launch_sdot(v.t, nullptr, H.d_D, sc, v.part, v.sc, SC_TT, st);
+  read_slot(H, v.sc, SC_TT, tt);
+  std::fill(act.begin(), act.end(), 1);
+  upload_act(H, act);
+  SPAQR_HIP(hipStreamSynchronize(st));  // h_act is reused by the next call
   H.kt.harvest();
-  const bool conv = res <= tol;
-  if (info) {
-    info->iters = it;
-    info->converged = conv ? 1 : 0;
-    info->residual = denom > 0 ? tt / denom : 0.0;
-    info->paper_residual = atb > 0 ? tt / atb : 0.0;
-    info->norm_a = normA;
-    info->seconds = now_s() - t0;
+  const double secs = now_s() - t0;
+  bool all = true;
+  for (int g = 0; g < G; ++g) {
+    const bool conv = res[g] <= tol;
+    all = all && conv;
+    if (infos) {
+      spaqr_cgls_info& info = infos[g];
+      const double trn = std::sqrt(tt[g]);
+      info.iters = iters[g];
+      info.converged = conv ? 1 : 0;
+      info.residual = denom[g] > 0 ? trn / denom[g] : 0.0;
+      info.paper_residual = atb[g] > 0 ? trn / atb[g] : 0.0;
+      info.norm_a = H.normA[g];
+      info.seconds = secs;
+    }
   }
-  return conv ? SPAQR_OK : SPAQR_NOCONV;
-}
-
-void scale_values(Handle& H) {
-  Vecs v = workspace(H);
-  const int64_t N = H.P.N, M = H.P.M;
-  hipStream_t st = H.stream;
-  SPAQR_HIP(hipMemsetAsync(H.d_flag, 0, sizeof(int), st));
-  launch_colscale(H.d_atp, H.d_atsrc, H.d_vals, N, H.d_D, H.d_ahat, H.d_ahatT, H.d_flag, st);
-  SPAQR_HIP(hipMemcpyAsync(H.h_sc + 8, H.d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
-  SPAQR_HIP(hipStreamSynchronize(st));
-  int bad = 0;
-  std::memcpy(&bad, H.h_sc + 8, sizeof(int));
-  if (bad) throw Error(SPAQR_EARG, "a column of A has zero norm");
-  // ||A||_2: 30 power steps on A^T A = D Ahat^T Ahat D from the all-ones
-  // vector (a lower bound of the norm)
-  launch_fill(v.p, 1.0 / std::sqrt((double)N), N, st);
-  for (int it = 0; it < 30; ++it) {
-    launch_scale(v.u, v.p, H.d_D, N, true, st);
-    amul(H, v.u, v.q);
-    atmul(H, v.q, v.t);
-    launch_scale(v.t, v.t, H.d_D, N, true, st);
-    launch_dot(v.t, nullptr, nullptr, N, v.part, v.sc + SC_PW, st);
-    launch_normalize(v.p, v.t, N, v.sc, SC_PW, st);
-  }
-  const double lam2 = read_scalar(H, v.sc + SC_PW);
-  H.normA = std::sqrt(std::sqrt(lam2));
-  (void)M;
+  return all ? SPAQR_OK : SPAQR_NOCONV;
 }
 
 int adjoint(Handle& H, const double* x, const double* b, const double* g, double tol, int max_iter,
             double* grad_b, double* grad_vals, double* lambda, spaqr_cgls_info* info) {
   if (!H.factored) throw Error(SPAQR_ESTATE, "factorize first");
+  if (H.P.count != 1) throw Error(SPAQR_EARG, "the adjoint solve takes a single-problem handle");
   if (!(tol >= 0.0) || max_iter < 0) throw Error(SPAQR_EARG, "bad tolerance or iteration limit");
   const double t0 = now_s();
   Vecs v = workspace(H);
   const int64_t N = H.P.N, M = H.P.M;
+  const Segs sc = cols(H);
   hipStream_t st = H.stream;
   // In mu = D lambda:  (Ahat^T Ahat) mu = D^-1 g, preconditioned by W^-1 W^-T.
   // v.y = mu, v.t = residual, v.s = z, v.p = search direction.
   launch_scale(v.t, g, H.d_D, N, false, st);
-  launch_dot(g, nullptr, nullptr, N, v.part, v.sc + SC_TRUE, st);
+  launch_sdot(g, nullptr, nullptr, sc, v.part, v.sc, SC_TRUE, st);
   launch_copy(v.s, v.t, N, st);
   apply_op(H, true, v.s);
   apply_op(H, false, v.s);
   launch_copy(v.p, v.s, N, st);
-  launch_dot(v.t, v.s, nullptr, N, v.part, v.sc + SC_G, st);
+  launch_sdot(v.t, v.s, nullptr, sc, v.part, v.sc, SC_G, st);
   SPAQR_HIP(hipMemsetAsync(v.y, 0, N * sizeof(double), st));
-  const double ng = std::sqrt(read_scalar(H, v.sc + SC_TRUE));
+  std::vector<double> tmp;
+  read_slot(H, v.sc, SC_TRUE, tmp);
+  const double ng = std::sqrt(tmp[0]);
   double res = ng > 0 ? 1.0 : 0.0;
   int it = 0;
   while (res > tol && it < max_iter) {
     amul(H, v.p, v.q);
     atmul(H, v.q, v.u);
-    launch_dot(v.p, v.u, nullptr, N, v.part, v.sc + SC_QQ, st);
-    launch_step(v.y, v.p, N, v.t, v.u, N, v.sc, st);
-    launch_dot(v.t, nullptr, H.d_D, N, v.part, v.sc + SC_TT, st);
+    launch_sdot(v.p, v.u, nullptr, sc, v.part, v.sc, SC_QQ, st);
+    launch_step(v.y, v.p, sc, v.t, v.u, sc, nullptr, v.sc, st);
+    launch_sdot(v.t, nullptr, H.d_D, sc, v.part, v.sc, SC_TT, st);
     launch_copy(v.s, v.t, N, st);
     apply_op(H, true, v.s);
     apply_op(H, false, v.s);
-    launch_dot(v.t, v.s, nullptr, N, v.part, v.sc + SC_GN, st);
-    launch_pupdate(v.p, v.s, N, v.sc, st);
-    launch_set(v.sc, SC_G, SC_GN, st);
+    launch_sdot(v.t, v.s, nullptr, sc, v.part, v.sc, SC_GN, st);
+    launch_pupdate(v.p, v.s, sc, nullptr, v.sc, st);
+    launch_set(v.sc, SC_G, SC_GN, nullptr, 1, st);
     ++it;
-    res = std::sqrt(read_scalar(H, v.sc + SC_TT)) / ng;
+    read_slot(H, v.sc, SC_TT, tmp);
+    res = std::sqrt(tmp[0]) / ng;
   }
   // lambda = D^-1 mu (into v.s), A lambda = Ahat mu (into v.q)
   launch_scale(v.s, v.y, H.d_D, N, false, st);
@@ -215,7 +276,7 @@ int adjoint(Handle& H, const double* x, const double* b, const double* g, double
   atmul(H, v.q, v.u);
   launch_scale(v.u, v.u, H.d_D, N, true, st);
   launch_sub(v.u, g, v.u, N, st);
-  launch_dot(v.u, nullptr, nullptr, N, v.part, v.sc + SC_TT, st);
+  launch_sdot(v.u, nullptr, nullptr, sc, v.part, v.sc, SC_TT, st);
   // r = b - A x = b - Ahat (D x)
   if (grad_vals) {
     launch_scale(v.t, x, H.d_D, N, true, st);
@@ -223,7 +284,8 @@ int adjoint(Handle& H, const double* x, const double* b, const double* g, double
     launch_sub(v.r, b, v.r, M, st);
     launch_adj_grad(H.d_rp, H.d_ci, v.r, v.q, v.s, x, M, grad_vals, st);
   }
-  const double tr = std::sqrt(read_scalar(H, v.sc + SC_TT));
+  read_slot(H, v.sc, SC_TT, tmp);
+  const double tr = std::sqrt(tmp[0]);
   H.kt.harvest();
   const bool conv = res <= tol;
   if (info) {
@@ -231,7 +293,7 @@ int adjoint(Handle& H, const double* x, const double* b, const double* g, double
     info->converged = conv ? 1 : 0;
     info->residual = ng > 0 ? tr / ng : 0.0;
     info->paper_residual = res;
-    info->norm_a = H.normA;
+    info->norm_a = H.normA[0];
     info->seconds = now_s() - t0;
   }
   return conv ? SPAQR_OK : SPAQR_NOCONV;

@@ -83,10 +83,22 @@ struct Plan {
   std::vector<int64_t> at_ptr;
   std::vector<int32_t> at_idx;
   std::vector<int64_t> at_src;      // CSR entry index of each A^T entry
+  // Independent problems held by the plan (a batch is the block-diagonal
+  // union): problem g owns columns [seg_col[g], seg_col[g+1]) and rows
+  // [seg_row[g], seg_row[g+1]).
+  int count = 1;
+  std::vector<int64_t> seg_col, seg_row;
+  std::vector<int> seg_depth;
 };
 
 void analyze_plan(Plan& P, const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                   int64_t M, int64_t N, const spaqr_options& opt);
+// Block-diagonal union of independently analysed plans.  Tree levels are
+// aligned from the leaves (a problem of depth d sits at levels
+// depth_max - d + 1 .. depth_max), so one level of the union holds the
+// same-level fronts of every problem.  All parts must share the
+// sparsification skip.
+void union_plans(Plan& U, std::vector<Plan>& parts);
 void rescale_values(Plan& P, const double* vals);
 
 // ---------------------------------------------------------------------------

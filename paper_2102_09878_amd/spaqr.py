@@ -22,8 +22,8 @@ WINV, WINVT = 0, 1
 
 EXPORTS = ["spaqr_analyze", "spaqr_get_ordering", "spaqr_set_values", "spaqr_factorize",
            "spaqr_factorize_forced", "spaqr_apply", "spaqr_apply_op", "spaqr_cgls", "spaqr_factor_stats",
-           "spaqr_get_ranks", "spaqr_get_op", "spaqr_time_kernel", "spaqr_adjoint", "spaqr_destroy",
-           "spaqr_last_error"]
+           "spaqr_get_ranks", "spaqr_get_op", "spaqr_time_kernel", "spaqr_adjoint", "spaqr_batch_analyze",
+           "spaqr_batch_info", "spaqr_batch_cgls", "spaqr_destroy", "spaqr_last_error"]
 
 
 class Options(ctypes.Structure):
@@ -82,6 +82,9 @@ def load(path: str = LIB_PATH):
         "spaqr_get_op": [P, I32, ctypes.POINTER(OpDesc), P, P, P, P],
         "spaqr_time_kernel": [P, ctypes.c_char_p, ctypes.c_int32],
         "spaqr_adjoint": [P, P, P, P, D, I32, P, P, P, ctypes.POINTER(CglsInfo)],
+        "spaqr_batch_analyze": [I32, P, P, P, P, P, P, ctypes.POINTER(P)],
+        "spaqr_batch_info": [P, ctypes.POINTER(I32), P, P],
+        "spaqr_batch_cgls": [P, P, D, I32, P, P],
         "spaqr_destroy": [P],
     }
     for name, args in sig.items():
@@ -194,6 +197,52 @@ def spaqr_adjoint(h, x_dev, b_dev, g_dev, grad_b_dev=None, grad_vals_dev=None, l
     _check(lib, h, rc, allow=(OK, NOCONV))
     return dict(iters=info.iters, converged=bool(info.converged), residual=info.residual,
                 recurrence_residual=info.paper_residual, seconds=info.seconds)
+
+
+def spaqr_batch_analyze(problems, depths, sparsify_skip=-1, sep_width=0, precision=FP64, device=0):
+    """problems: sequence of (row_ptr, col_idx, vals, M, N, grid)."""
+    lib = load()
+    keep = []
+    n = len(problems)
+    rps, cis, vas = (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)()
+    Ms, Ns = np.zeros(n, dtype=np.int64), np.zeros(n, dtype=np.int64)
+    opts = (Options * n)()
+    for g, (rp, ci, va, M, N, grid) in enumerate(problems):
+        rp = np.ascontiguousarray(rp, dtype=np.int64)
+        ci = np.ascontiguousarray(ci, dtype=np.int32)
+        va = np.ascontiguousarray(va, dtype=np.float64)
+        keep += [rp, ci, va]
+        rps[g], cis[g], vas[g] = rp.ctypes.data, ci.ctypes.data, va.ctypes.data
+        Ms[g], Ns[g] = M, N
+        gr = list(grid) + [1] * (3 - len(grid))
+        opts[g] = Options(int(depths[g]), sparsify_skip, (ctypes.c_int32 * 3)(*gr), sep_width, precision, device,
+                          None)
+    h = ctypes.c_void_p()
+    rc = lib.spaqr_batch_analyze(n, ctypes.cast(rps, ctypes.c_void_p), ctypes.cast(cis, ctypes.c_void_p),
+                                 ctypes.cast(vas, ctypes.c_void_p), _ptr(Ms), _ptr(Ns),
+                                 ctypes.cast(opts, ctypes.c_void_p), ctypes.byref(h))
+    _check(lib, None, rc)
+    return h
+
+
+def spaqr_batch_info(h):
+    lib = load()
+    n = ctypes.c_int32()
+    _check(lib, h, lib.spaqr_batch_info(h, ctypes.byref(n), None, None))
+    co = np.zeros(n.value + 1, dtype=np.int64)
+    ro = np.zeros(n.value + 1, dtype=np.int64)
+    _check(lib, h, lib.spaqr_batch_info(h, ctypes.byref(n), _ptr(co), _ptr(ro)))
+    return co, ro
+
+
+def spaqr_batch_cgls(h, b_dev, x_dev, count, tol=1e-10, max_iter=200):
+    lib = load()
+    infos = (CglsInfo * count)()
+    rc = lib.spaqr_batch_cgls(h, _ptr(_dev_f64(b_dev)), float(tol), int(max_iter), _ptr(_dev_f64(x_dev)),
+                              ctypes.cast(infos, ctypes.c_void_p))
+    _check(lib, h, rc, allow=(OK, NOCONV))
+    return [dict(iters=i.iters, converged=bool(i.converged), residual=i.residual,
+                 paper_residual=i.paper_residual, norm_a=i.norm_a, seconds=i.seconds) for i in infos]
 
 
 def spaqr_factor_stats(h):
@@ -328,3 +377,33 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class BatchSolver(Solver):
+    """Independent problems factorized together (one launch per round for
+    all of them) and solved by per-problem CGLS.  Batch vectors hold the
+    members back to back (offsets ``col_off`` / ``row_off``)."""
+
+    def __init__(self, problems, depths, skip=-1, sep_width=0, precision="fp64", device=0):
+        prec = {"fp64": FP64, "fp32": FP32_FACTOR}[precision]
+        self.h = spaqr_batch_analyze(problems, depths, skip, sep_width, prec, device)
+        self.col_off, self.row_off = spaqr_batch_info(self.h)
+        self.count = len(self.col_off) - 1
+        self.M, self.N = int(self.row_off[-1]), int(self.col_off[-1])
+        self.nnz = int(sum(len(p[1]) for p in problems))
+        self.version = 0
+
+    @classmethod
+    def from_problems(cls, probs, depths, skip=-1, precision="fp64"):
+        return cls([(p.row_ptr, p.col_idx, p.vals, p.M, p.N, p.grid) for p in probs], depths, skip,
+                   precision=precision)
+
+    def cgls_each(self, b_dev, tol=1e-10, max_iter=200):
+        """x (batch order) and one info dict per member."""
+        import torch
+        x = torch.empty(self.N, dtype=torch.float64, device=b_dev.device)
+        infos = spaqr_batch_cgls(self.h, b_dev, x, self.count, tol, max_iter)
+        return x, infos
+
+    def adjoint(self, *a, **k):
+        raise SpaqrError(EARG, "the adjoint solve takes a single-problem Solver")

@@ -125,3 +125,39 @@ def test_factorize_without_gpu_reports_hip_error():
         s.factorize(1e-2)
     assert e.value.code == b.EHIP
     s.close()
+
+
+def test_batch_analysis_is_the_union_of_members():
+    """A batch handle orders each member exactly as its own analysis does,
+    at the member's column offset (integer parity, host only)."""
+    probs = [grid_ls((s, s + 3), s * (s + 3), 40 + s) for s in (9, 14, 11)]
+    depths = [3, 4, 3]
+    bs = pk.BatchSolver.from_problems(probs, depths, skip=1)
+    assert bs.count == 3
+    assert list(bs.col_off) == [0] + list(np.cumsum([p.N for p in probs]))
+    assert list(bs.row_off) == [0] + list(np.cumsum([p.M for p in probs]))
+    perm, owner = bs.ordering()
+    fbase = 0
+    for g, (p, d) in enumerate(zip(probs, depths)):
+        an = osp.analyze(p, d)
+        c0, c1 = bs.col_off[g], bs.col_off[g + 1]
+        r0, r1 = bs.row_off[g], bs.row_off[g + 1]
+        assert (perm[c0:c1] == an.col_perm + c0).all()
+        assert (owner[r0:r1] == an.row_owner + fbase).all()
+        fbase += int(an.row_owner.max()) + 1
+    bs.close()
+
+
+def test_batch_rejects_mixed_skip_and_bad_member():
+    def member(p, grid=None):
+        return (p.row_ptr, p.col_idx, p.vals, p.M, p.N, grid or p.grid)
+
+    p1, p2 = grid_ls((24, 24), 576, 1), grid_ls((24, 24), 576, 2)
+    # default skip is 1 at depth 4 and 2 at depth 5
+    with pytest.raises(pk.SpaqrError) as e:
+        pk.BatchSolver([member(p1), member(p2)], [4, 5], skip=-1)
+    assert e.value.code == b.EARG and "sparsify_skip" in str(e.value)
+    # a member whose grid does not match its N is named in the message
+    with pytest.raises(pk.SpaqrError) as e:
+        pk.BatchSolver([member(p1), member(p2, (24, 23))], [4, 4], skip=1)
+    assert e.value.code == b.EARG and "batch member 1" in str(e.value)
