@@ -22,7 +22,6 @@ namespace {
 
 constexpr int BS = 256;
 constexpr int APPLY_MAX = 4096;  // largest cluster handled by one block (32 KB LDS vector)
-constexpr int XN_CHUNK = 2048;   // neighbour values staged in LDS per pass (16 KB)
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -93,10 +92,9 @@ __device__ void trsv_upper_t(const T* __restrict__ R, int64_t ld, int n, double*
 
 template <typename T>
 __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, int transpose,
-                                              double* __restrict__ x, double* __restrict__ stage) {
+                                              double* __restrict__ x, double* __restrict__ work) {
   const ApplyOp op = ops[blockIdx.x];
   __shared__ double t[APPLY_MAX];
-  __shared__ double xn[XN_CHUNK];
   __shared__ double sh[4];
   const int tid = threadIdx.x;
   const int n1 = op.n1;
@@ -105,66 +103,23 @@ __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, i
   for (int i = tid; i < n1; i += BS) t[i] = x[op.s1[i]];
   __syncthreads();
   if (op.kind == 0) {  // eliminate
-    const int cN = op.n2;
-    const T* RN = R + (int64_t)n1 * op.ld;
+    const double* pw = work + op.poff;
     if (!transpose) {
-      // t -= R_sN x_N.  x_N is staged in LDS chunk by chunk; when the
-      // cluster has fewer rows than threads, threads split the columns into
-      // `ns` slices and the slices are summed at the end.
-      const int ns = n1 >= BS ? 1 : BS / n1;
-      const int my_i = n1 >= BS ? 0 : tid % n1, my_s = n1 >= BS ? 0 : tid / n1;
-      double acc_s = 0.0;
-      for (int cb = 0; cb < cN; cb += XN_CHUNK) {
-        const int ce = min(cN, cb + XN_CHUNK);
-        __syncthreads();
-        for (int c = cb + tid; c < ce; c += BS) xn[c - cb] = x[op.s2[c]];
-        __syncthreads();
-        if (n1 >= BS) {
-          for (int i = tid; i < n1; i += BS) {
-            double acc = 0.0;
-            for (int c = cb; c < ce; ++c) acc += (double)RN[i + (int64_t)c * op.ld] * xn[c - cb];
-            t[i] -= acc;
-          }
-        } else if (my_s < ns) {
-          for (int c = cb + my_s; c < ce; c += ns) acc_s += (double)RN[my_i + (int64_t)c * op.ld] * xn[c - cb];
-        }
-      }
-      if (n1 < BS) {
-        __syncthreads();
-        if (my_s < ns) xn[tid] = acc_s;
-        __syncthreads();
-        if (tid < n1) {
+      // t = x_s - R_sN x_N from the chunk partials (summed in chunk order)
+      if (op.n2 > 0)
+        for (int i = tid; i < n1; i += BS) {
           double a = 0.0;
-          for (int s = 0; s < ns; ++s) a += xn[s * n1 + tid];
-          t[tid] -= a;
+          for (int k = 0; k < op.nchunk; ++k) a += pw[(int64_t)k * n1 + i];
+          t[i] -= a;
         }
-      }
       __syncthreads();
       trsv_upper(R, op.ld, n1, t);
       for (int i = tid; i < n1; i += BS) x[op.s1[i]] = t[i];
     } else {
       trsv_upper_t(R, op.ld, n1, t);
-      for (int i = tid; i < n1; i += BS) x[op.s1[i]] = t[i];
-      // R_sN^T t to the staging buffer; neighbours shared by several ops
-      // of the round are summed afterwards in op order
-      double* out = stage + op.nstage;
-      if (cN >= BS) {
-        // one column per thread: each thread streams its own column of R_sN
-        for (int c = tid; c < cN; c += BS) {
-          const T* col = RN + (int64_t)c * op.ld;
-          double acc = 0.0;
-          for (int i = 0; i < n1; ++i) acc += (double)col[i] * t[i];
-          out[c] = acc;
-        }
-      } else {
-        const int w = tid >> 6, lane = tid & 63;
-        for (int c = w; c < cN; c += 4) {
-          const T* col = RN + (int64_t)c * op.ld;
-          double acc = 0.0;
-          for (int i = lane; i < n1; i += 64) acc += (double)col[i] * t[i];
-          acc = wave_sum(acc);
-          if (lane == 0) out[c] = acc;
-        }
+      for (int i = tid; i < n1; i += BS) {
+        x[op.s1[i]] = t[i];
+        if (op.n2 > 0) work[op.poff + i] = t[i];
       }
     }
   } else if (op.kind == 1) {  // scale
@@ -176,17 +131,106 @@ __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, i
   } else {  // sparsify: Q = H_0 .. H_{r-1}
     const int r = op.n2;
     const T* tau = static_cast<const T*>(op.tau);
-    for (int s = 0; s < r; ++s) {
-      const int k = transpose ? s : r - 1 - s;
-      const T* v = R + (int64_t)k * op.ld;
-      double part = 0.0;
-      for (int i = k + tid; i < n1; i += BS) part += (double)v[i] * t[i];
-      const double dot = block_sum(part, sh);
-      const double f = (double)tau[k] * dot;
-      for (int i = k + tid; i < n1; i += BS) t[i] -= f * (double)v[i];
+    if (n1 <= 256) {
+      // one wave: a lane owns entries lane, lane + 64, ..., so the
+      // reflectors need no barrier, only a wave reduction each
+      if (tid < 64) {
+        for (int s = 0; s < r; ++s) {
+          const int k = transpose ? s : r - 1 - s;
+          const T* v = R + (int64_t)k * op.ld;
+          double part = 0.0;
+          for (int i = k + tid; i < n1; i += 64) part += (double)v[i] * t[i];
+          const double f = (double)tau[k] * wave_sum(part);
+          for (int i = k + tid; i < n1; i += 64) t[i] -= f * (double)v[i];
+        }
+      }
       __syncthreads();
+    } else {
+      for (int s = 0; s < r; ++s) {
+        const int k = transpose ? s : r - 1 - s;
+        const T* v = R + (int64_t)k * op.ld;
+        double part = 0.0;
+        for (int i = k + tid; i < n1; i += BS) part += (double)v[i] * t[i];
+        const double dot = block_sum(part, sh);
+        const double f = (double)tau[k] * dot;
+        for (int i = k + tid; i < n1; i += BS) t[i] -= f * (double)v[i];
+        __syncthreads();
+      }
     }
     for (int i = tid; i < n1; i += BS) x[op.s1[i]] = t[i];
+  }
+}
+
+// One (op, chunk) of the neighbour products, columns [c0, c0 + APPLY_CHUNK).
+// W^-1: work[poff + k n1 + i] = sum_c R_sN[i, c] x[s2[c]]; the chunk's x
+// values are staged in LDS and rows are spread over the threads (when n1 is
+// small the threads also split the columns, summed in a fixed order).
+// W^-T: stage[nstage + c] = sum_i R_sN[i, c] t_i with t from work[poff ..];
+// each wave takes four columns at a time, lanes over rows (coalesced).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_apply_gemv(const ApplyOp* __restrict__ ops, const int2* __restrict__ chunks,
+                                                   int transpose, const double* __restrict__ x,
+                                                   double* __restrict__ stage, double* __restrict__ work) {
+  const int2 ck = chunks[blockIdx.x];
+  const ApplyOp op = ops[ck.x];
+  const int n1 = op.n1;
+  const int c0 = ck.y * APPLY_CHUNK, c1 = min(op.n2, c0 + APPLY_CHUNK);
+  const T* RN = static_cast<const T*>(op.R) + (int64_t)n1 * op.ld;
+  const int tid = threadIdx.x;
+  __shared__ double v[APPLY_MAX > APPLY_CHUNK ? APPLY_MAX : APPLY_CHUNK];
+  if (!transpose) {
+    for (int c = c0 + tid; c < c1; c += BS) v[c - c0] = x[op.s2[c]];
+    __syncthreads();
+    double* out = work + op.poff + (int64_t)ck.y * n1;
+    const int rows = (n1 + 63) / 64 * 64;
+    const int ns = rows >= BS ? 1 : BS / rows;  // column slices
+    const int sl = tid / rows, i0 = tid % rows;
+    __shared__ double part[BS];
+    for (int ib = 0; ib < n1; ib += (rows >= BS ? BS : rows)) {
+      const int i = ib + (rows >= BS ? tid : i0);
+      double acc = 0.0;
+      if (sl < ns && i < n1)
+        for (int c = c0 + sl; c < c1; c += ns) acc += (double)RN[i + (int64_t)c * op.ld] * v[c - c0];
+      if (ns == 1) {
+        if (sl == 0 && i < n1) out[i] = acc;
+      } else {
+        part[tid] = acc;
+        __syncthreads();
+        if (sl == 0 && i < n1) {
+          double a = 0.0;
+          for (int k = 0; k < ns; ++k) a += part[k * rows + i0];
+          out[i] = a;
+        }
+        __syncthreads();
+      }
+    }
+  } else {
+    for (int i = tid; i < n1; i += BS) v[i] = work[op.poff + i];
+    __syncthreads();
+    const int wv = tid >> 6, lane = tid & 63;
+    for (int cb = c0 + 4 * wv; cb < c1; cb += 16) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      const T* col = RN + (int64_t)cb * op.ld;
+      const int nc = min(4, c1 - cb);
+      for (int i = lane; i < n1; i += 64) {
+        const double ti = v[i];
+        a0 += (double)col[i] * ti;
+        if (nc > 1) a1 += (double)col[i + op.ld] * ti;
+        if (nc > 2) a2 += (double)col[i + 2 * op.ld] * ti;
+        if (nc > 3) a3 += (double)col[i + 3 * op.ld] * ti;
+      }
+      a0 = wave_sum(a0);
+      a1 = wave_sum(a1);
+      a2 = wave_sum(a2);
+      a3 = wave_sum(a3);
+      if (lane == 0) {
+        double* out = stage + op.nstage + cb;
+        out[0] = a0;
+        if (nc > 1) out[1] = a1;
+        if (nc > 2) out[2] = a2;
+        if (nc > 3) out[3] = a3;
+      }
+    }
   }
 }
 
@@ -215,10 +259,20 @@ __global__ void k_spmv(const int64_t* __restrict__ ptr, const int32_t* __restric
 
 template <typename T>
 void launch_apply_batch(const ApplyOp* d_ops, int n, int max_n1, bool transpose, double* x,
-                        double* stage, hipStream_t s) {
+                        double* stage, double* work, hipStream_t s) {
   if (n <= 0) return;
   if (max_n1 > APPLY_MAX) throw Error(SPAQR_EARG, "cluster too large for the apply kernel");
-  hipLaunchKernelGGL(k_apply<T>, dim3(n), dim3(BS), 0, s, d_ops, transpose ? 1 : 0, x, stage);
+  (void)stage;
+  hipLaunchKernelGGL(k_apply<T>, dim3(n), dim3(BS), 0, s, d_ops, transpose ? 1 : 0, x, work);
+  SPAQR_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_apply_gemv(const ApplyOp* d_ops, const int2* chunks, int nchunks, bool transpose, const double* x,
+                       double* stage, double* work, hipStream_t s) {
+  if (nchunks <= 0) return;
+  hipLaunchKernelGGL(k_apply_gemv<T>, dim3(nchunks), dim3(BS), 0, s, d_ops, chunks, transpose ? 1 : 0, x, stage,
+                     work);
   SPAQR_HIP(hipGetLastError());
 }
 
@@ -237,7 +291,11 @@ void launch_spmv(const int64_t* ptr, const int32_t* idx, const double* val, cons
   SPAQR_HIP(hipGetLastError());
 }
 
-template void launch_apply_batch<double>(const ApplyOp*, int, int, bool, double*, double*, hipStream_t);
-template void launch_apply_batch<float>(const ApplyOp*, int, int, bool, double*, double*, hipStream_t);
+template void launch_apply_batch<double>(const ApplyOp*, int, int, bool, double*, double*, double*, hipStream_t);
+template void launch_apply_batch<float>(const ApplyOp*, int, int, bool, double*, double*, double*, hipStream_t);
+template void launch_apply_gemv<double>(const ApplyOp*, const int2*, int, bool, const double*, double*, double*,
+                                        hipStream_t);
+template void launch_apply_gemv<float>(const ApplyOp*, const int2*, int, bool, const double*, double*, double*,
+                                       hipStream_t);
 
 }  // namespace spaqr

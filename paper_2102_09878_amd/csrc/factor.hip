@@ -369,6 +369,9 @@ class Factorizer {
     }
     std::fprintf(stderr, "[spaqr] L%d r%d %-8s count %4zu max_m %5d max_n %6d sum_mn %.3e\n", level_, round_,
                  what, v.size(), mm, mn, work);
+    static const bool each = on && std::getenv("SPAQR_DEBUG_SHAPES")[0] == '2';
+    if (each)
+      for (auto& d : v) std::fprintf(stderr, "[spaqr]   %s L%d r%d m %d n %d\n", what, level_, round_, d.m, d.n);
   }
 
   // grow-only device scratch (valid for the whole factorization)
@@ -737,7 +740,9 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
     od[e].colmap = dop + od_cm[e];
     od[e].cl_off = dop + od_off[e];
   }
-  launch_owner<T>(upload(od), (int)od.size(), st);
+  int od_rows = 0;
+  for (const OwnerDesc& o : od) od_rows = std::max(od_rows, o.nrows);
+  launch_owner<T>(upload(od), (int)od.size(), od_rows, st);
   ++launches_;
   int* h_owner = static_cast<int*>(H.stage.alloc((std::max<size_t>(1, nown) + qe.size()) * sizeof(int)));
   int* h_rank = h_owner + std::max<size_t>(1, nown);
@@ -1193,7 +1198,7 @@ void Factorizer<T>::reassign_group_rows(int gi) {
   d.lda = src.ld;
   d.nrows = src.nrows;
   d.ncl = (int)src.clus.size();
-  launch_owner<T>(upload(std::vector<OwnerDesc>{d}), 1, st);
+  launch_owner<T>(upload(std::vector<OwnerDesc>{d}), 1, d.nrows, st);
   int* h = static_cast<int*>(H.stage.alloc(src.nrows * sizeof(int)));
   SPAQR_HIP(hipMemcpyAsync(h, d_owner, src.nrows * sizeof(int), hipMemcpyDeviceToHost, st));
   sync();
@@ -1280,7 +1285,7 @@ template <typename T>
 void Factorizer<T>::build_apply() {
   H.batches.clear();
   size_t i = 0;
-  int64_t max_stage = 0;
+  int64_t max_stage = 0, max_work = 0;
   while (i < H.ops.size()) {
     size_t j = i;
     while (j < H.ops.size() && H.ops[j].level == H.ops[i].level && H.ops[j].phase == H.ops[i].phase &&
@@ -1299,6 +1304,8 @@ void Factorizer<T>::build_apply() {
     // neighbour contributions of the eliminations (W^-T): staging offsets
     // per op, and per touched slot the list of offsets in op order
     int nstage = 0;
+    int64_t pw = 0;
+    std::vector<int2> chunks;
     std::vector<std::pair<int, int>> contrib;  // (slot, staging offset), op order within a slot
     for (size_t k = i; k < j; ++k) {
       OpRec& o = H.ops[k];
@@ -1314,10 +1321,16 @@ void Factorizer<T>::build_apply() {
       a.n2 = o.n2;
       a.kind = o.kind;
       a.nstage = 0;
+      a.poff = 0;
+      a.nchunk = 0;
       if (o.kind == 0 && o.n1 > 0 && o.n2 > 0) {
         a.nstage = nstage;
         for (int c = 0; c < o.n2; ++c) contrib.push_back({o.s2[c], nstage + c});
         nstage += o.n2;
+        a.nchunk = (o.n2 + APPLY_CHUNK - 1) / APPLY_CHUNK;
+        a.poff = pw;
+        pw += (int64_t)o.n1 * a.nchunk;
+        for (int k = 0; k < a.nchunk; ++k) chunks.push_back(make_int2((int)ao.size(), k));
       }
       ao.push_back(a);
       mx = std::max(mx, o.n1);
@@ -1333,6 +1346,11 @@ void Factorizer<T>::build_apply() {
     b.d_ops = upload(ao);
     b.n = (int)ao.size();
     b.max_n1 = mx;
+    if (!chunks.empty()) {
+      b.d_chunks = upload(chunks);
+      b.nchunks = (int)chunks.size();
+      max_work = std::max(max_work, pw);
+    }
     if (!contrib.empty()) {
       std::stable_sort(contrib.begin(), contrib.end(),
                        [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first < b.first; });
@@ -1355,6 +1373,7 @@ void Factorizer<T>::build_apply() {
     i = j;
   }
   H.d_nstage = max_stage > 0 ? static_cast<double*>(H.arena.alloc(max_stage * sizeof(double))) : nullptr;
+  H.d_awork = max_work > 0 ? static_cast<double*>(H.arena.alloc(max_work * sizeof(double))) : nullptr;
 }
 
 template <typename T>
@@ -1478,10 +1497,23 @@ void apply_op(Handle& H, bool transpose, double* x) {
     const ApplyBatch& b = H.batches[transpose ? k : nb - 1 - k];
     const bool timed = H.kt.pick("apply");
     if (timed) H.kt.mark(H.stream);
-    if (H.precision == SPAQR_FP32_FACTOR)
-      launch_apply_batch<float>(b.d_ops, b.n, b.max_n1, transpose, x, H.d_nstage, H.stream);
+    const bool f32 = H.precision == SPAQR_FP32_FACTOR;
+    if (!transpose && b.nchunks > 0) {
+      if (f32)
+        launch_apply_gemv<float>(b.d_ops, b.d_chunks, b.nchunks, false, x, H.d_nstage, H.d_awork, H.stream);
+      else
+        launch_apply_gemv<double>(b.d_ops, b.d_chunks, b.nchunks, false, x, H.d_nstage, H.d_awork, H.stream);
+    }
+    if (f32)
+      launch_apply_batch<float>(b.d_ops, b.n, b.max_n1, transpose, x, H.d_nstage, H.d_awork, H.stream);
     else
-      launch_apply_batch<double>(b.d_ops, b.n, b.max_n1, transpose, x, H.d_nstage, H.stream);
+      launch_apply_batch<double>(b.d_ops, b.n, b.max_n1, transpose, x, H.d_nstage, H.d_awork, H.stream);
+    if (transpose && b.nchunks > 0) {
+      if (f32)
+        launch_apply_gemv<float>(b.d_ops, b.d_chunks, b.nchunks, true, x, H.d_nstage, H.d_awork, H.stream);
+      else
+        launch_apply_gemv<double>(b.d_ops, b.d_chunks, b.nchunks, true, x, H.d_nstage, H.d_awork, H.stream);
+    }
     if (transpose && b.n_nslots > 0)
       launch_apply_nsum(b.d_nslots, b.d_nptr, b.d_noff, b.n_nslots, H.d_nstage, x, H.stream);
     if (timed) {

@@ -33,6 +33,9 @@ struct ApplyBatch {
   const int* d_nptr = nullptr;
   const int* d_noff = nullptr;
   int n_nslots = 0;
+  // (op, chunk) work-groups of the elimination neighbour products
+  const int2* d_chunks = nullptr;
+  int nchunks = 0;
   double bytes = 0.0;  // algorithmic bytes of one application of the batch
   double flops = 0.0;
 };
@@ -111,6 +114,7 @@ struct Handle {
   std::vector<OpRec> ops;
   std::vector<ApplyBatch> batches;
   double* d_nstage = nullptr;  // contributions R_sN^T x_s of one batch (arena)
+  double* d_awork = nullptr;   // chunk partials / t vectors of one batch (arena)
   std::vector<int> ranks;
   spaqr_stats stats{};
   KernelTimer kt;

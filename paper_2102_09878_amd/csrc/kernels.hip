@@ -11,6 +11,8 @@
 //    of reassigned rows (Section 2.3), row copies, identity writes.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include <cfloat>
 #include <cmath>
 
@@ -142,16 +144,25 @@ __global__ __launch_bounds__(BS) void k_trsm(const TrsmDesc* __restrict__ D) {
   }
 }
 
-// owner of each row: cluster with the largest sum of squared entries
+// owner of each row: cluster with the largest sum of squared entries, the
+// first (lowest) cluster on ties.  A work-group covers 64 rows (one per
+// lane, coalesced column reads); its 4 waves take every 4th cluster and
+// their best (value, cluster) pairs are merged in LDS.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_owner(const OwnerDesc* __restrict__ D) {
   const OwnerDesc d = D[blockIdx.x];
   const T* A = static_cast<const T*>(d.A);
   const int nrows = d.nrows_dev ? d.nrows_dev[0] : d.nrows;
-  for (int r = threadIdx.x; r < nrows; r += BS) {
-    int best = 0;
-    double bv = -1.0;
-    for (int q = 0; q < d.ncl; ++q) {
+  const int r0 = blockIdx.y * 64;
+  if (r0 >= nrows) return;  // uniform over the block
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = r0 + lane;
+  __shared__ double sv[4][64];
+  __shared__ int sq[4][64];
+  int best = INT_MAX;
+  double bv = -1.0;
+  if (r < nrows)
+    for (int q = wv; q < d.ncl; q += 4) {
       double s = 0.0;
       for (int c = d.cl_off[q]; c < d.cl_off[q + 1]; ++c) {
         const double v = A[r + (int64_t)d.colmap[c] * d.lda];
@@ -159,7 +170,13 @@ __global__ __launch_bounds__(BS) void k_owner(const OwnerDesc* __restrict__ D) {
       }
       if (s > bv) bv = s, best = q;
     }
-    d.owner[r] = best;
+  sv[wv][lane] = bv;
+  sq[wv][lane] = best;
+  __syncthreads();
+  if (wv == 0 && r < nrows) {
+    for (int w = 1; w < 4; ++w)
+      if (sv[w][lane] > bv || (sv[w][lane] == bv && sq[w][lane] < best)) bv = sv[w][lane], best = sq[w][lane];
+    d.owner[r] = best == INT_MAX ? 0 : best;
   }
 }
 
@@ -261,9 +278,9 @@ void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, hipStream_t s) {
 }
 
 template <typename T>
-void launch_owner(const OwnerDesc* d_desc, int n, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_owner<T>, dim3(n), dim3(BS), 0, s, d_desc);
+void launch_owner(const OwnerDesc* d_desc, int n, int max_rows, hipStream_t s) {
+  if (n <= 0 || max_rows <= 0) return;
+  hipLaunchKernelGGL(k_owner<T>, dim3(n, (max_rows + 63) / 64), dim3(BS), 0, s, d_desc);
   SPAQR_HIP(hipGetLastError());
 }
 
@@ -293,7 +310,7 @@ void launch_scatter(const ScatterDesc* d_desc, int n, hipStream_t s) {
   template void launch_gather<T>(const GatherDesc*, int, int, hipStream_t);                    \
   template void launch_scatter_csr<T>(T*, const int64_t*, const double*, int64_t, hipStream_t); \
   template void launch_trsm<T>(const TrsmDesc*, int, int, hipStream_t);                             \
-  template void launch_owner<T>(const OwnerDesc*, int, hipStream_t);                           \
+  template void launch_owner<T>(const OwnerDesc*, int, int, hipStream_t);                           \
   template void launch_rowcopy<T>(const RowCopyDesc*, int, int, hipStream_t);                         \
   template void launch_extract<T>(const ExtractDesc*, int, hipStream_t);                       \
   template void launch_scatter<T>(const ScatterDesc*, int, hipStream_t);

@@ -58,17 +58,62 @@ __device__ __forceinline__ void house_scalars(double alpha, double xn2, double& 
   }
 }
 
-// T of the compact-WY form from tau and the strictly-upper Gram G[a][b] = v_a^T v_b
-__device__ void build_t(double* Tm, const double* s_tau, const double (*G)[NB + 1], int kb) {
+// T of the compact-WY form (upper triangular, kb x kb, stored NB x NB
+// row-major at Tg) from tau and the strictly-upper Gram G[a][b] = v_a^T v_b:
+// T[i][i] = tau_i, T[a][i] = -tau_i sum_{b=a}^{i-1} T[a][b] G[b][i].  Built
+// in LDS column by column (threads over rows a), then written out.  All
+// threads of the block must call it.
+__device__ void build_t(double* __restrict__ Tg, const double* s_tau, const double (*G)[NB + 1], int kb,
+                        double (*Ts)[NB + 1]) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NB * NB; e += BS) Ts[e / NB][e % NB] = 0.0;
+  __syncthreads();
   for (int i = 0; i < kb; ++i) {
-    Tm[i * NB + i] = s_tau[i];
-    for (int a = 0; a < i; ++a) {
+    if (tid < i) {
       double acc = 0.0;
-      for (int b = a; b < i; ++b) acc += Tm[a * NB + b] * G[b][i];
-      Tm[a * NB + i] = -s_tau[i] * acc;
+      for (int b = tid; b < i; ++b) acc += Ts[tid][b] * G[b][i];
+      Ts[tid][i] = -s_tau[i] * acc;
+    } else if (tid == i) {
+      Ts[i][i] = s_tau[i];
     }
-    for (int a = i + 1; a < NB; ++a) Tm[a * NB + i] = 0.0;
+    __syncthreads();
   }
+  for (int e = tid; e < NB * NB; e += BS) Tg[e] = Ts[e / NB][e % NB];
+}
+
+// Partial Gram of the panel's reflectors over rows [r0, r1): out[a][b] for
+// a < b < kb of sum_r v_a[r] v_b[r], where v_a has 1 at row j0+a, zeros
+// above and the stored reflector below.  64-row tiles of V go through LDS;
+// thread t accumulates entries (t / 8, 4 (t % 8) .. + 3).  All threads of
+// the block must call it.
+template <typename T>
+__device__ void gram_rows(const T* __restrict__ A, int64_t lda, int j0, int kb, int r0, int r1,
+                          double (*Vs)[NB + 1], double* acc4) {
+  const int tid = threadIdx.x;
+  const int a = tid >> 3, b0 = (tid & 7) * 4;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) acc4[k] = 0.0;
+  for (int rb = r0; rb < r1; rb += 64) {
+    __syncthreads();
+    for (int e = tid; e < 64 * NB; e += BS) {
+      const int rr = e & 63, c = e >> 6;
+      const int r = rb + rr;
+      double v = 0.0;
+      if (r < r1 && c < kb) {
+        const int rc = j0 + c;
+        v = r == rc ? 1.0 : (r > rc ? (double)A[r + (int64_t)rc * lda] : 0.0);
+      }
+      Vs[rr][c] = v;
+    }
+    __syncthreads();
+    const int nr = min(64, r1 - rb);
+    for (int rr = 0; rr < nr; ++rr) {
+      const double va = Vs[rr][a];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc4[k] += va * Vs[rr][b0 + k];
+    }
+  }
+  __syncthreads();
 }
 
 __device__ __forceinline__ int seg_lo(int j0) { return j0 / RS; }
@@ -77,6 +122,13 @@ __device__ __forceinline__ int seg_hi(int m) { return (m + RS - 1) / RS; }
 // ---------------------------------------------------------------------------
 // panel, one work-group per front
 // ---------------------------------------------------------------------------
+// Each thread owns the rows j0 + tid + k BS of the panel for the whole
+// panel, so a column step needs no data exchange besides the block
+// reductions: (a) ||tail||^2 and alpha -> reflector scalars, (b) scale the
+// owned part of v_i, (c) one accumulation pass over the owned rows forming
+// the kb-1 dot products v_i^T y_j (j > i, trailing panel columns) and
+// v_a^T v_i (a < i, Gram column of T) together, (d) update the owned rows
+// and extend T by one column in LDS.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_qr_panel(const QRDesc* __restrict__ D, int j0,
                                                  double* __restrict__ tbuf) {
@@ -90,56 +142,93 @@ __global__ __launch_bounds__(BS) void k_qr_panel(const QRDesc* __restrict__ D, i
   const int m = d.m;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   __shared__ double sh[4];
-  __shared__ double s_tau[NB];
-  __shared__ double G[NB][NB + 1];
+  __shared__ double red[4][NB];
+  __shared__ double sv[NB];
+  __shared__ double gcol[NB];
+  __shared__ double fj[NB];
+  __shared__ double Ts[NB][NB + 1];
 
+  for (int e = tid; e < NB * NB; e += BS) Ts[e / NB][e % NB] = 0.0;
   for (int i = 0; i < kb; ++i) {
     const int c = j0 + i;
-    T* col = A + c * lda;
+    T* col = A + (int64_t)c * lda;
+    // (a)
     double part = 0.0;
-    for (int r = c + 1 + tid; r < m; r += BS) {
-      const double v = col[r];
-      part += v * v;
-    }
+    for (int r = j0 + tid; r < m; r += BS)
+      if (r > c) {
+        const double v = col[r];
+        part += v * v;
+      }
     const double xn2 = block_sum(part, sh);
     const double alpha = col[c];
     double beta, tv, scal;
     house_scalars(alpha, xn2, beta, tv, scal);
+    const double tvT = (double)static_cast<T>(tv);
+    // (b)
     if (tv != 0.0)
-      for (int r = c + 1 + tid; r < m; r += BS) col[r] = static_cast<T>(col[r] * scal);
+      for (int r = j0 + tid; r < m; r += BS)
+        if (r > c) col[r] = static_cast<T>(col[r] * scal);
+    // (c) value q: a = q for q < i (Gram), column j = q + 1 for q >= i (dots)
+    double acc[NB - 1];
+#pragma unroll
+    for (int q = 0; q < NB - 1; ++q) acc[q] = 0.0;
+    for (int r = j0 + tid; r < m; r += BS) {
+      if (r <= c) continue;
+      const double vi = col[r];
+#pragma unroll
+      for (int q = 0; q < NB - 1; ++q)
+        if (q < kb - 1) acc[q] += vi * (double)A[r + (int64_t)(j0 + (q < i ? q : q + 1)) * lda];
+    }
+#pragma unroll
+    for (int q = 0; q < NB - 1; ++q) {
+      if (q < kb - 1) {
+        const double w = wave_sum(acc[q]);
+        if (lane == 0) red[wv][q] = w;
+      }
+    }
     __syncthreads();
+    if (tid < kb - 1) sv[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    __syncthreads();
+    // (d)
+    if (tid < kb - 1) {
+      if (tid < i) {
+        gcol[tid] = sv[tid] + (double)A[c + (int64_t)(j0 + tid) * lda];
+      } else {
+        const T* y = A + (int64_t)(j0 + tid + 1) * lda;
+        fj[tid + 1] = tv * (sv[tid] + (double)y[c]);
+      }
+    }
+    __syncthreads();
+    if (tid < i) {
+      double a2 = 0.0;
+      for (int b2 = tid; b2 < i; ++b2) a2 += Ts[tid][b2] * gcol[b2];
+      Ts[tid][i] = -tvT * a2;
+    } else if (tid == i) {
+      Ts[i][i] = tvT;
+    }
     if (tv != 0.0) {
-      for (int cc = c + 1 + wv; cc < j0 + kb; cc += 4) {
-        T* y = A + cc * lda;
-        const double yc = y[c];
-        double dot = 0.0;
-        for (int r = c + 1 + lane; r < m; r += 64) dot += (double)col[r] * (double)y[r];
-        dot = wave_sum(dot) + yc;
-        const double f = tv * dot;
-        if (lane == 0) y[c] = static_cast<T>(yc - f);
-        for (int r = c + 1 + lane; r < m; r += 64) y[r] = static_cast<T>(y[r] - f * (double)col[r]);
+      for (int r = j0 + tid; r < m; r += BS) {
+        if (r <= c) continue;
+        const double vi = col[r];
+        for (int j = i + 1; j < kb; ++j) {
+          T* y = A + (int64_t)(j0 + j) * lda + r;
+          *y = static_cast<T>((double)*y - fj[j] * vi);
+        }
+      }
+      if (tid >= i && tid < kb - 1) {
+        T* y = A + (int64_t)(j0 + tid + 1) * lda + c;
+        *y = static_cast<T>((double)*y - fj[tid + 1]);
       }
     }
     __syncthreads();
     if (tid == 0) {
       col[c] = static_cast<T>(beta);
       tau[c] = static_cast<T>(tv);
-      s_tau[i] = static_cast<double>(static_cast<T>(tv));
     }
     __syncthreads();
   }
-  for (int pr = wv; pr < kb * kb; pr += 4) {
-    const int a = pr / kb, b = pr % kb;
-    if (a >= b) continue;
-    const T* va = A + (j0 + a) * lda;
-    const T* vb = A + (j0 + b) * lda;
-    double dot = 0.0;
-    for (int r = j0 + b + 1 + lane; r < m; r += 64) dot += (double)va[r] * (double)vb[r];
-    dot = wave_sum(dot);
-    if (lane == 0) G[a][b] = dot + (double)va[j0 + b];
-  }
-  __syncthreads();
-  if (tid == 0) build_t(tbuf + (int64_t)blockIdx.x * NB * NB, s_tau, G, kb);
+  double* Tg = tbuf + (int64_t)blockIdx.x * NB * NB;
+  for (int e = tid; e < NB * NB; e += BS) Tg[e] = Ts[e / NB][e % NB];
 }
 
 // ---------------------------------------------------------------------------
@@ -259,19 +348,14 @@ __global__ __launch_bounds__(BS) void k_qrp_gram(const QRDesc* __restrict__ D, i
   const int64_t lda = d.lda;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   double* gp = ws.gp + ((int64_t)f * ws.MS + s) * NB * NB;
-  for (int pr = wv; pr < kb * kb; pr += 4) {
-    const int a = pr / kb, b = pr % kb;
-    if (a >= b) continue;
-    const T* va = A + (int64_t)(j0 + a) * lda;
-    const T* vb = A + (int64_t)(j0 + b) * lda;
-    double dot = 0.0;
-    for (int r = max(r0, j0 + b + 1) + lane; r < r1; r += 64) dot += (double)va[r] * (double)vb[r];
-    dot = wave_sum(dot);
-    if (lane == 0) {
-      const int rb = j0 + b;
-      gp[a * NB + b] = dot + ((rb >= r0 && rb < r1) ? (double)va[rb] : 0.0);
-    }
-  }
+  __shared__ double Vs[64][NB + 1];
+  double acc4[4];
+  gram_rows(A, lda, j0, kb, r0, r1, Vs, acc4);
+  const int a = tid >> 3, b0 = (tid & 7) * 4;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) gp[a * NB + b0 + k] = acc4[k];
+  (void)wv;
+  (void)lane;
 }
 
 template <typename T>
@@ -283,6 +367,7 @@ __global__ __launch_bounds__(BS) void k_qrp_tmat(const QRDesc* __restrict__ D, i
   const int f = blockIdx.x;
   __shared__ double G[NB][NB + 1];
   __shared__ double s_tau[NB];
+  __shared__ double Ts[NB][NB + 1];
   for (int e = threadIdx.x; e < NB * NB; e += BS) {
     const int a = e / NB, b = e % NB;
     double acc = 0.0;
@@ -292,7 +377,7 @@ __global__ __launch_bounds__(BS) void k_qrp_tmat(const QRDesc* __restrict__ D, i
   }
   if (threadIdx.x < kb) s_tau[threadIdx.x] = (double)static_cast<const T*>(d.tau)[j0 + threadIdx.x];
   __syncthreads();
-  if (threadIdx.x == 0) build_t(ws.tbuf + (int64_t)f * NB * NB, s_tau, G, kb);
+  build_t(ws.tbuf + (int64_t)f * NB * NB, s_tau, G, kb, Ts);
 }
 
 // ---------------------------------------------------------------------------

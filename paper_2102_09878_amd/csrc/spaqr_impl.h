@@ -211,7 +211,8 @@ struct TrsmDesc {
 // owner[i] = argmax over clusters q of sum_{c in q} A[i, colmap[c]]^2 for
 // i < nrows, cluster q owning colmap entries [cl_off[q], cl_off[q+1]);
 // first maximum wins.  nrows_dev (when set) holds the row count on the
-// device, e.g. the rank just chosen by a rank-revealing QR.
+// device, e.g. the rank just chosen by a rank-revealing QR; nrows is then
+// its upper bound.
 struct OwnerDesc {
   const void* A;
   const int* colmap;
@@ -268,7 +269,16 @@ struct ApplyOp {
   int n1, n2;          // eliminate: c_s, c_N; scale: c_p, 0; sparsify: c_p, r
   int kind;
   int nstage;          // eliminate, W^-T: offset of R_sN^T x_s in the staging buffer
+  int64_t poff;        // eliminate: offset of its vectors in the work buffer (see below)
+  int nchunk, pad_;    // eliminate: column chunks of R_sN (APPLY_CHUNK columns each)
 };
+// Neighbour products of the eliminations are split over column chunks of
+// R_sN, one work-group per (op, chunk):
+//  W^-1: work[poff + k * n1 + i] = sum over chunk k of R_sN[i, c] x_N[c], then
+//        the op's work-group uses x_s - sum_k work[poff + k * n1 ..];
+//  W^-T: the op's work-group writes t = R_ss^-T x_s to work[poff ..], then
+//        stage[nstage + c] = R_sN[:, c]^T t per chunk.
+constexpr int APPLY_CHUNK = 256;
 
 // ---------------------------------------------------------------------------
 // Launchers (kernels.hip, apply.hip)
@@ -316,7 +326,7 @@ void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int st
 template <typename T>
 void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, hipStream_t s);
 template <typename T>
-void launch_owner(const OwnerDesc* d_desc, int n, hipStream_t s);
+void launch_owner(const OwnerDesc* d_desc, int n, int max_rows, hipStream_t s);
 template <typename T>
 void launch_rowcopy(const RowCopyDesc* d_desc, int n, int max_cols, hipStream_t s);
 template <typename T>
@@ -330,7 +340,11 @@ void launch_scatter(const ScatterDesc* d_desc, int n, hipStream_t s);
 // (deterministic, no atomics).
 template <typename T>
 void launch_apply_batch(const ApplyOp* d_ops, int n, int max_n1, bool transpose, double* x,
-                        double* stage, hipStream_t s);
+                        double* stage, double* work, hipStream_t s);
+// chunk work-groups of the eliminations of a batch: chunks[k] = (op, chunk)
+template <typename T>
+void launch_apply_gemv(const ApplyOp* d_ops, const int2* chunks, int nchunks, bool transpose, const double* x,
+                       double* stage, double* work, hipStream_t s);
 void launch_apply_nsum(const int* nslots, const int* nptr, const int* noff, int n, const double* stage,
                        double* x, hipStream_t s);
 
