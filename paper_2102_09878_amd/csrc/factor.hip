@@ -1284,16 +1284,30 @@ void Factorizer<T>::merge(int m) {
 template <typename T>
 void Factorizer<T>::build_apply() {
   H.batches.clear();
-  size_t i = 0;
+  // Batches of the W sweeps.  Only slot overlap orders the ops here: an op
+  // goes to the batch after every earlier op that wrote one of its slots
+  // (s1, or an eliminated cluster's neighbours s2) and after every earlier
+  // elimination that had one of its own slots s1 as a neighbour.  Two
+  // eliminations may share neighbours (their updates are summed per slot).
+  // Ops inside a batch touch disjoint slots otherwise, so they commute, and
+  // W^-1 / W^-T apply the batches backward / forward.
+  std::vector<int> last_w(P.N, -1), last_n(P.N, -1);
+  std::vector<std::vector<int>> groups;
+  for (size_t k = 0; k < H.ops.size(); ++k) {
+    const OpRec& o = H.ops[k];
+    int b = 0;
+    for (int t : o.s1) b = std::max(b, std::max(last_w[t], last_n[t]) + 1);
+    for (int t : o.s2) b = std::max(b, last_w[t] + 1);
+    for (int t : o.s1) last_w[t] = std::max(last_w[t], b);
+    for (int t : o.s2) last_n[t] = std::max(last_n[t], b);
+    if ((int)groups.size() <= b) groups.resize(b + 1);
+    groups[b].push_back((int)k);
+  }
   int64_t max_stage = 0, max_work = 0;
-  while (i < H.ops.size()) {
-    size_t j = i;
-    while (j < H.ops.size() && H.ops[j].level == H.ops[i].level && H.ops[j].phase == H.ops[i].phase &&
-           H.ops[j].round == H.ops[i].round)
-      ++j;
+  for (const std::vector<int>& grp : groups) {
     IntPool pool;
     std::vector<size_t> o1, o2;
-    for (size_t k = i; k < j; ++k) {
+    for (int k : grp) {
       o1.push_back(pool.add(H.ops[k].s1));
       o2.push_back(pool.add(H.ops[k].s2));
     }
@@ -1307,10 +1321,10 @@ void Factorizer<T>::build_apply() {
     int64_t pw = 0;
     std::vector<int2> chunks;
     std::vector<std::pair<int, int>> contrib;  // (slot, staging offset), op order within a slot
-    for (size_t k = i; k < j; ++k) {
-      OpRec& o = H.ops[k];
-      o.d_s1 = dp + o1[k - i];
-      o.d_s2 = dp + o2[k - i];
+    for (size_t gi = 0; gi < grp.size(); ++gi) {
+      OpRec& o = H.ops[grp[gi]];
+      o.d_s1 = dp + o1[gi];
+      o.d_s2 = dp + o2[gi];
       ApplyOp a{};
       a.R = o.R;
       a.tau = o.tau;
@@ -1370,7 +1384,6 @@ void Factorizer<T>::build_apply() {
       max_stage = std::max<int64_t>(max_stage, nstage);
     }
     H.batches.push_back(b);
-    i = j;
   }
   H.d_nstage = max_stage > 0 ? static_cast<double*>(H.arena.alloc(max_stage * sizeof(double))) : nullptr;
   H.d_awork = max_work > 0 ? static_cast<double*>(H.arena.alloc(max_work * sizeof(double))) : nullptr;
