@@ -231,6 +231,156 @@ __global__ __launch_bounds__(BS) void k_qr_panel(const QRDesc* __restrict__ D, i
   for (int e = tid; e < NB * NB; e += BS) Tg[e] = Ts[e / NB][e % NB];
 }
 
+// Same column steps with the panel held in registers (FP32 fronts of at
+// most 2048 rows below j0): 512 threads, thread t owning rows j0 + t + 512 k
+// (k < 4) of all NB panel columns.  The owner of row c = j0 + i publishes
+// that row to LDS at the start of step i; everything else stays in
+// registers until the panel is written back once at the end.
+constexpr int PBS = 512;
+constexpr int PRPT = 4;
+
+__device__ __forceinline__ double block_sum8(double v, double* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return ((sh[0] + sh[1]) + (sh[2] + sh[3])) + ((sh[4] + sh[5]) + (sh[6] + sh[7]));
+}
+
+// One column step of the register panel; I is a compile-time column so all
+// register indexing is static.
+template <int I>
+__device__ __forceinline__ void panel_step(float (&P)[PRPT][NB], int j0, int m, int kb, float* tau,
+                                           double* sh, double (*red)[NB], double* sv, double* gcol, double* fj,
+                                           double* rowc, double (*Ts)[NB + 1]) {
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int c = j0 + I;
+  const int oc = I % PBS, kc = I / PBS;
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < PRPT; ++k) {
+    const int r = j0 + tid + PBS * k;
+    if (r > c && r < m) part += (double)P[k][I] * (double)P[k][I];
+    if (tid == oc && k == kc)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) rowc[q] = P[k][q];
+  }
+  const double xn2 = block_sum8(part, sh);
+  const double alpha = rowc[I];
+  double beta, tv, scal;
+  house_scalars(alpha, xn2, beta, tv, scal);
+  const double tvT = (double)static_cast<float>(tv);
+  // a thread sums its (at most PRPT) rows in FP32, the reduction is FP64
+  float acc[NB - 1];
+#pragma unroll
+  for (int q = 0; q < NB - 1; ++q) acc[q] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < PRPT; ++k) {
+    const int r = j0 + tid + PBS * k;
+    if (r <= c || r >= m) continue;
+    if (tv != 0.0) P[k][I] = static_cast<float>(P[k][I] * scal);
+    const float vi = P[k][I];
+#pragma unroll
+    for (int q = 0; q < NB - 1; ++q) acc[q] = fmaf(vi, P[k][q < I ? q : q + 1], acc[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < NB - 1; ++q) {
+    if (q < kb - 1) {
+      const double w = wave_sum((double)acc[q]);
+      if (lane == 0) red[wv][q] = w;
+    }
+  }
+  __syncthreads();
+  if (tid < kb - 1)
+    sv[tid] = ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) +
+              ((red[4][tid] + red[5][tid]) + (red[6][tid] + red[7][tid]));
+  __syncthreads();
+  if (tid < kb - 1) {
+    if (tid < I)
+      gcol[tid] = sv[tid] + rowc[tid];
+    else
+      fj[tid + 1] = tv * (sv[tid] + rowc[tid + 1]);
+  }
+  __syncthreads();
+  if (tid < I) {
+    double a2 = 0.0;
+    for (int b2 = tid; b2 < I; ++b2) a2 += Ts[tid][b2] * gcol[b2];
+    Ts[tid][I] = -tvT * a2;
+  } else if (tid == I) {
+    Ts[I][I] = tvT;
+  }
+#pragma unroll
+  for (int k = 0; k < PRPT; ++k) {
+    const int r = j0 + tid + PBS * k;
+    if (r < c || r >= m) continue;
+    const double vi = P[k][I];
+    if (r == c) {
+#pragma unroll
+      for (int q = I + 1; q < NB; ++q)
+        if (q < kb && tv != 0.0) P[k][q] = static_cast<float>((double)P[k][q] - fj[q]);
+      P[k][I] = static_cast<float>(beta);
+    } else if (tv != 0.0) {
+#pragma unroll
+      for (int q = I + 1; q < NB; ++q)
+        if (q < kb) P[k][q] = static_cast<float>((double)P[k][q] - fj[q] * vi);
+    }
+  }
+  if (tid == 0) tau[c] = static_cast<float>(tv);
+  __syncthreads();
+}
+
+template <int I>
+__device__ __forceinline__ void panel_steps(float (&P)[PRPT][NB], int j0, int m, int kb, float* tau, double* sh,
+                                            double (*red)[NB], double* sv, double* gcol, double* fj, double* rowc,
+                                            double (*Ts)[NB + 1]) {
+  if constexpr (I < NB) {
+    if (I >= kb) return;
+    panel_step<I>(P, j0, m, kb, tau, sh, red, sv, gcol, fj, rowc, Ts);
+    panel_steps<I + 1>(P, j0, m, kb, tau, sh, red, sv, gcol, fj, rowc, Ts);
+  }
+}
+
+__global__ __launch_bounds__(PBS) void k_qr_panel_reg(const QRDesc* __restrict__ D, int j0,
+                                                      double* __restrict__ tbuf) {
+  const QRDesc d = D[blockIdx.x];
+  const int kk = min(d.m, d.k);
+  if (j0 >= kk) return;
+  const int kb = min(NB, kk - j0);
+  float* A = static_cast<float*>(d.A);
+  float* tau = static_cast<float*>(d.tau);
+  const int64_t lda = d.lda;
+  const int m = d.m;
+  const int tid = threadIdx.x;
+  __shared__ double sh[8];
+  __shared__ double red[8][NB];
+  __shared__ double sv[NB];
+  __shared__ double gcol[NB];
+  __shared__ double fj[NB];
+  __shared__ double rowc[NB];
+  __shared__ double Ts[NB][NB + 1];
+
+  float P[PRPT][NB];
+#pragma unroll
+  for (int k = 0; k < PRPT; ++k) {
+    const int r = j0 + tid + PBS * k;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) P[k][q] = (r < m && q < kb) ? A[r + (int64_t)(j0 + q) * lda] : 0.0f;
+  }
+  for (int e = tid; e < NB * NB; e += PBS) Ts[e / NB][e % NB] = 0.0;
+  __syncthreads();
+  panel_steps<0>(P, j0, m, kb, tau, sh, red, sv, gcol, fj, rowc, Ts);
+#pragma unroll
+  for (int k = 0; k < PRPT; ++k) {
+    const int r = j0 + tid + PBS * k;
+    if (r < m)
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        if (q < kb) A[r + (int64_t)(j0 + q) * lda] = P[k][q];
+  }
+  double* Tg = tbuf + (int64_t)blockIdx.x * NB * NB;
+  for (int e = tid; e < NB * NB; e += PBS) Tg[e] = Ts[e / NB][e % NB];
+}
+
 // ---------------------------------------------------------------------------
 // panel, row-split (tall fronts)
 // ---------------------------------------------------------------------------
@@ -567,6 +717,9 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork&
       hipLaunchKernelGGL(k_qrp_gram<T>, g, dim3(BS), 0, s, d_desc, j0, ws);
       hipLaunchKernelGGL(k_qrp_tmat<T>, dim3(nf), dim3(BS), 0, s, d_desc, j0, ws);
       *launches += 2;
+    } else if (sizeof(T) == 4 && mmax - j0 <= PBS * PRPT) {
+      hipLaunchKernelGGL(k_qr_panel_reg, dim3(nf), dim3(PBS), 0, s, d_desc, j0, ws.tbuf);
+      ++*launches;
     } else {
       hipLaunchKernelGGL(k_qr_panel<T>, dim3(nf), dim3(BS), 0, s, d_desc, j0, ws.tbuf);
       ++*launches;
