@@ -668,6 +668,125 @@ __global__ __launch_bounds__(BS) void k_qru_apply(const QRDesc* __restrict__ D, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// trailing update on the matrix cores (FP32 fronts)
+//
+// v_mfma_f32_16x16x4f32, one 16x16 block per wave: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] (K = 4), and holds
+// D[4 (l / 16) + v][l % 16] in accumulator v.  FP32 accumulation.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// W_s = V_s^T C_s for one (front, 64-column tile, row segment): output
+// 32 x 64; wave w computes a-rows 16 (w & 1) .. +16 and two 16-column
+// blocks 2 (w >> 1), 2 (w >> 1) + 1, over 64-row slabs staged in LDS.
+__global__ __launch_bounds__(BS) void k_qru_w_mfma(const QRDesc* __restrict__ D, int j0, QRWork ws) {
+  const QRDesc d = D[blockIdx.x];
+  const int kk = min(d.m, d.k);
+  if (j0 >= kk) return;
+  const int kb = min(NB, kk - j0);
+  const int t = blockIdx.y, s = blockIdx.z;
+  const int c0 = j0 + kb + t * TN;
+  if (c0 >= d.n) return;
+  const int m = d.m;
+  const int r0 = max(j0, s * RS), r1 = min(m, (s + 1) * RS);
+  if (r0 >= r1) return;
+  const int nc = min(TN, d.n - c0);
+  const float* A = static_cast<const float*>(d.A);
+  const int64_t lda = d.lda;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  __shared__ float Vs[64][NB + 1];
+  __shared__ float Cs[64][TN + 1];
+  const int ab = wv & 1, jb = 2 * (wv >> 1);
+  const int li = lane & 15, lk = lane >> 4;
+  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  for (int rb = r0; rb < r1; rb += 64) {
+    __syncthreads();
+    for (int e = tid; e < 64 * NB; e += BS) {
+      const int rr = e & 63, a = e >> 6;
+      const int r = rb + rr;
+      Vs[rr][a] = r < r1 ? vref(A, lda, j0, a, kb, r) : 0.0f;
+    }
+    for (int e = tid; e < 64 * TN; e += BS) {
+      const int rr = e & 63, cc = e >> 6;
+      const int r = rb + rr;
+      Cs[rr][cc] = (r < r1 && cc < nc) ? A[r + (int64_t)(c0 + cc) * lda] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < 16; ++k4) {
+      const int rr = 4 * k4 + lk;
+      const float av = Vs[rr][16 * ab + li];
+      acc0 = mfma16(av, Cs[rr][16 * jb + li], acc0);
+      acc1 = mfma16(av, Cs[rr][16 * (jb + 1) + li], acc1);
+    }
+  }
+  double* out = ws.wp + (((int64_t)blockIdx.x * ws.MT + t) * ws.MS + s) * NB * TN;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int a = 16 * ab + 4 * lk + v;
+    out[a * TN + 16 * jb + li] = (double)acc0[v];
+    out[a * TN + 16 * (jb + 1) + li] = (double)acc1[v];
+  }
+}
+
+// C_s -= V_s W for one (front, 64-column tile, row segment), computed as
+// (W^T V_s^T)^T so that a lane's accumulators run along rows: wave w owns
+// columns 16 w .. +16 of the tile and the four 16-row blocks of each
+// 64-row slab; K = kb <= 32 in steps of 4.
+__global__ __launch_bounds__(BS) void k_qru_apply_mfma(const QRDesc* __restrict__ D, int j0, QRWork ws) {
+  const QRDesc d = D[blockIdx.x];
+  const int kk = min(d.m, d.k);
+  if (j0 >= kk) return;
+  const int kb = min(NB, kk - j0);
+  const int t = blockIdx.y, s = blockIdx.z;
+  const int c0 = j0 + kb + t * TN;
+  if (c0 >= d.n) return;
+  const int m = d.m;
+  const int r0 = max(j0, s * RS), r1 = min(m, (s + 1) * RS);
+  if (r0 >= r1) return;
+  const int nc = min(TN, d.n - c0);
+  float* A = static_cast<float*>(d.A);
+  const int64_t lda = d.lda;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  __shared__ float Ws[NB][TN + 1];
+  __shared__ float Vs[64][NB + 1];
+  const double* win = ws.w + ((int64_t)blockIdx.x * ws.MT + t) * NB * TN;
+  for (int e = tid; e < NB * TN; e += BS) Ws[e / TN][e % TN] = (float)win[e];
+  const int li = lane & 15, lk = lane >> 4;
+  const int col = 16 * wv + 4 * lk;  // first of this lane's four columns
+  for (int rb = r0; rb < r1; rb += 64) {
+    __syncthreads();
+    for (int e = tid; e < 64 * NB; e += BS) {
+      const int rr = e & 63, a = e >> 6;
+      const int r = rb + rr;
+      Vs[rr][a] = r < r1 ? vref(A, lda, j0, a, kb, r) : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k4 = 0; k4 < NB / 4; ++k4) {
+        const int a = 4 * k4 + lk;
+        acc = mfma16(Ws[a][16 * wv + li], Vs[16 * b + li][a], acc);
+      }
+      const int r = rb + 16 * b + li;
+      if (r < r1)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (col + v < nc) {
+            float* p = A + r + (int64_t)(c0 + col + v) * lda;
+            *p = *p - acc[v];
+          }
+    }
+  }
+}
+
 }  // namespace
 
 void qr_work_dims(const std::vector<QRDesc>& h, int* MS, int* MT) {
@@ -727,9 +846,15 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork&
     SPAQR_HIP(hipGetLastError());
     if (tiles > 0) {
       const dim3 g3(nf, tiles, segs), g2(nf, tiles);
-      hipLaunchKernelGGL(k_qru_w<T>, g3, dim3(BS), 0, s, d_desc, j0, ws);
+      if (sizeof(T) == 4)
+        hipLaunchKernelGGL(k_qru_w_mfma, g3, dim3(BS), 0, s, d_desc, j0, ws);
+      else
+        hipLaunchKernelGGL(k_qru_w<T>, g3, dim3(BS), 0, s, d_desc, j0, ws);
       hipLaunchKernelGGL(k_qru_reduce<T>, g2, dim3(BS), 0, s, d_desc, j0, ws);
-      hipLaunchKernelGGL(k_qru_apply<T>, g3, dim3(BS), 0, s, d_desc, j0, ws);
+      if (sizeof(T) == 4)
+        hipLaunchKernelGGL(k_qru_apply_mfma, g3, dim3(BS), 0, s, d_desc, j0, ws);
+      else
+        hipLaunchKernelGGL(k_qru_apply<T>, g3, dim3(BS), 0, s, d_desc, j0, ws);
       SPAQR_HIP(hipGetLastError());
       *launches += 3;
     }

@@ -91,6 +91,19 @@ def test_config1_factor_parity_forced_ranks(cfg1):
     s.close()
 
 
+@pytest.mark.parametrize("grid,depth,skip,eps", [((32, 32), 4, 1, 1e-2), ((48, 40), 5, 2, 1e-2)])
+def test_fp32_factor_close_to_oracle(grid, depth, skip, eps):
+    """FP32 fronts and factors, same ranks as the FP64 oracle: every factor
+    op within about a hundred FP32 roundings of the oracle's."""
+    p = grid_ls(grid, grid[0] * grid[1], 31)
+    an, f = _oracle(p, depth, eps, skip)
+    s = pk.Solver.from_problem(p, depth, skip, precision="fp32")
+    s.factorize(eps, ranks=f.ranks)
+    worst = _compare_ops(f, s, 2e-5)
+    print(f"fp32 {grid}: worst relative factor difference {worst:.3e}")
+    s.close()
+
+
 def test_config1_factor_deterministic(cfg1):
     c, p, an, f = cfg1
     s = pk.Solver.from_problem(p, c["depth"], c["skip"])
