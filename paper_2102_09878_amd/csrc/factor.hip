@@ -411,10 +411,15 @@ class Factorizer {
   void run_pqr(std::vector<PQRDesc>& q) {
     if (q.empty()) return;
     int total = 0, kmax = 0, max_m = 1, live_m = 0;
+    for (const PQRDesc& e : q) max_m = std::max(max_m, e.m);
+    // 8-column chunks: wider ones (fewer partials to scan, more columns per
+    // wave) measured slower at every matrix height here
+    const int cw = PQR_CW;
     std::vector<int2> bmap;
     for (size_t k = 0; k < q.size(); ++k) {
+      q[k].cw = cw;
       q[k].blk0 = total;
-      q[k].nblk = std::max(1, (q[k].n + PQR_CW - 1) / PQR_CW);
+      q[k].nblk = std::max(1, (q[k].n + cw - 1) / cw);
       for (int c = 0; c < q[k].nblk; ++c) bmap.push_back(make_int2((int)k, c));
       total += q[k].nblk;
       kmax = std::max(kmax, std::min(q[k].m, q[k].n));
@@ -437,7 +442,7 @@ class Factorizer {
         H.kt.mark(st);
         timed_steps_.push_back(steps);
       }
-      launch_pqr_step<T>(d, total, total, states, parts, dmap, active, steps, eps_, max_m, st);
+      launch_pqr_step<T>(d, total, total, states, parts, dmap, active, steps, eps_, max_m, cw, st);
       if (timed) H.kt.mark(st);
       ++launches_;
       ++steps;

@@ -30,6 +30,8 @@ namespace spaqr {
 namespace {
 
 constexpr int BS = 256;
+constexpr int PL = 6;  // chunk partials per thread fetched up front
+static_assert(PQR_CW == 8, "a pivot step gives each of its 4 waves cw/4 columns");
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(BS) void k_pqr_init(const PQRDesc* __restrict__ D,
   double* vn1 = d.work;
   double* vn2 = d.work + d.n;
   double* done = d.work + 2 * d.n;
-  const int c0 = bm.y * PQR_CW, c1 = min(d.n, c0 + PQR_CW);
+  const int c0 = bm.y * d.cw, c1 = min(d.n, c0 + d.cw);
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   __shared__ double sh[4];
   __shared__ double shv[4];
@@ -139,7 +141,11 @@ __global__ __launch_bounds__(BS) void k_pqr_init(const PQRDesc* __restrict__ D,
   }
 }
 
-template <typename T>
+// PQ: rows per lane held in registers for this work-group's columns (the
+// launcher picks 2 or 4 when that covers the batch's tallest matrix; 0
+// keeps the columns in memory, which measured faster for taller ones).
+// NC = cw / 4 columns per wave.
+template <typename T, int PQ, int NC>
 __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, PQRState* __restrict__ S,
                                                  PQRPart* __restrict__ parts, int total_parts,
                                                  const int2* __restrict__ bmap, int* __restrict__ active,
@@ -148,9 +154,14 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
   __shared__ double sh[4];
   __shared__ double shv[4];
   __shared__ int shi[4];
+  // Loads are issued in the order they are needed (they complete in
+  // order): block map with the first descriptor (most batches of single
+  // large matrices need no second round trip), state and chunk partials,
+  // then this work-group's own columns, which are consumed last.
   const int2 bm = bmap[blockIdx.x];
+  const PQRDesc d0 = D[0];
   const int mi = bm.x, ch = bm.y;
-  const PQRDesc d = D[mi];
+  const PQRDesc d = mi == 0 ? d0 : D[mi];
   const PQRState sp = S[2 * mi + (i & 1)];
   PQRState* sn = S + 2 * mi + ((i + 1) & 1);
   const PQRPart* prd = parts + (size_t)(i & 1) * total_parts;
@@ -158,11 +169,47 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
   T* A = static_cast<T*>(d.A);
   const int64_t lda = d.lda;
   const int m = d.m, n = d.n;
-  const int c0 = ch * PQR_CW, c1 = min(n, c0 + PQR_CW);
+  const int c0 = ch * d.cw, c1 = min(n, c0 + d.cw);
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   double* vn1 = d.work;
   double* vn2 = d.work + n;
   double* done = d.work + 2 * n;
+  double pval[PL];
+  int pidx[PL];
+  double pfro[PL];
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int k = tid + u * BS;
+    if (k < d.nblk) {
+      const PQRPart q = prd[d.blk0 + k];
+      pval[u] = q.val, pidx[u] = q.idx, pfro[u] = q.fro;
+    } else {
+      pval[u] = -1.0, pidx[u] = INT_MAX, pfro[u] = 0.0;
+    }
+  }
+  const bool regs = PQ > 0 && m - i <= 64 * PQ;
+  int jcol[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) jcol[k] = c0 + wv + 4 * k;
+  double yv[NC][PQ > 0 ? PQ : 1];
+  double v1p[NC], v2p[NC], dnp[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) v1p[k] = 0.0, v2p[k] = 1.0, dnp[k] = 1.0;
+  if (regs) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int j = jcol[k] < c1 ? jcol[k] : c0;
+      const T* y = A + (int64_t)j * lda;
+#pragma unroll
+      for (int q = 0; q < PQ; ++q) {
+        const int r = i + lane + 64 * q;
+        yv[k][q] = r < m ? (double)y[r] : 0.0;
+      }
+      dnp[k] = done[j];
+      v1p[k] = vn1[j];
+      v2p[k] = vn2[j];
+    }
+  }
 
   // finalise the previous pivot column (idempotent; every reader is done with it)
   if (sp.pivot >= c0 && sp.pivot < c1) {
@@ -177,7 +224,12 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
   // global pivot and (first step) the Frobenius norm
   double bv = -1.0, fro = 0.0;
   int bi = INT_MAX;
-  for (int k = tid; k < d.nblk; k += BS) {
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    if (pval[u] > bv || (pval[u] == bv && pidx[u] < bi)) bv = pval[u], bi = pidx[u];
+    fro += pfro[u];
+  }
+  for (int k = tid + PL * BS; k < d.nblk; k += BS) {
     const PQRPart q = prd[d.blk0 + k];
     if (q.val > bv || (q.val == bv && q.idx < bi)) bv = q.val, bi = q.idx;
     fro += q.fro;
@@ -244,7 +296,55 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
   }
   // apply H_i to the chunk's live columns and downdate their norms
   const double tol3z = sqrt(DBL_EPSILON);
-  for (int j = c0 + wv; j < c1; j += 4) {
+  if (regs) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int j = jcol[k];
+      if (j >= c1 || j == p || dnp[k] != 0.0) continue;
+      T* y = A + (int64_t)j * lda;
+      double dot = 0.0;
+      if (tv != 0.0)
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+          const int r = i + lane + 64 * q;
+          if (r < m) dot += x[r - i] * yv[k][q];
+        }
+      dot = wave_sum(dot);
+      const double f = tv * dot;
+      const double yi = __shfl(yv[k][0], 0, 64) - f;
+      if (tv != 0.0)
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+          const int r = i + lane + 64 * q;
+          if (r < m) {
+            const T nv = static_cast<T>(yv[k][q] - f * x[r - i]);
+            y[r] = nv;
+            yv[k][q] = (double)nv;
+          }
+        }
+      const double v1 = v1p[k];
+      if (v1 != 0.0) {
+        const double ay = fabs((double)static_cast<T>(yi));
+        double temp = 1.0 - (ay / v1) * (ay / v1);
+        temp = temp > 0.0 ? temp : 0.0;
+        const double ratio = v1 / v2p[k];
+        const double temp2 = temp * ratio * ratio;
+        if (temp2 <= tol3z) {
+          double s2 = 0.0;
+#pragma unroll
+          for (int q = 0; q < PQ; ++q) {
+            const int r = i + lane + 64 * q;
+            if (r > i && r < m) s2 += yv[k][q] * yv[k][q];
+          }
+          s2 = sqrt(wave_sum(s2));
+          if (lane == 0) vn1[j] = s2, vn2[j] = s2;
+        } else if (lane == 0) {
+          vn1[j] = v1 * sqrt(temp);
+        }
+      }
+    }
+  }
+  for (int j = c0 + wv; !regs && j < c1; j += 4) {
     if (j == p || done[j] != 0.0) continue;
     T* y = A + (int64_t)j * lda;
     double dot = 0.0;
@@ -310,13 +410,26 @@ void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPa
 
 template <typename T>
 void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRState* states,
-                     PQRPart* parts, const int2* bmap, int* active, int i, double eps, int max_m,
+                     PQRPart* parts, const int2* bmap, int* active, int i, double eps, int max_m, int cw,
                      hipStream_t s) {
   if (nblocks <= 0) return;
   const size_t lds = (size_t)std::max(1, max_m) * sizeof(double);
   if (lds > 64 * 1024) throw Error(SPAQR_EARG, "rank-revealing QR block taller than 8192 rows");
-  hipLaunchKernelGGL(k_pqr_step<T>, dim3(nblocks), dim3(BS), lds, s, d_desc, states, parts, total_parts,
-                     bmap, active, i, eps);
+  const int rows = max_m - i;
+#define SPAQR_PQR_GO(Q, C)                                                                                   \
+  hipLaunchKernelGGL((k_pqr_step<T, Q, C>), dim3(nblocks), dim3(BS), lds, s, d_desc, states, parts, total_parts, \
+                     bmap, active, i, eps)
+  if (cw == PQR_CW) {
+    if (rows <= 128)
+      SPAQR_PQR_GO(2, PQR_CW / 4);
+    else if (rows <= 256)
+      SPAQR_PQR_GO(4, PQR_CW / 4);
+    else
+      SPAQR_PQR_GO(0, PQR_CW / 4);
+  } else {
+    throw Error(SPAQR_EARG, "internal: unsupported pivot chunk width");
+  }
+#undef SPAQR_PQR_GO
   SPAQR_HIP(hipGetLastError());
 }
 
@@ -330,7 +443,7 @@ void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int st
 #define SPAQR_PQR_INST(T)                                                                             \
   template void launch_pqr_init<T>(const PQRDesc*, int, PQRState*, PQRPart*, const int2*, hipStream_t); \
   template void launch_pqr_step<T>(const PQRDesc*, int, int, PQRState*, PQRPart*, const int2*, int*, int, \
-                                   double, int, hipStream_t);                                         \
+                                   double, int, int, hipStream_t);                                    \
   template void launch_pqr_finish<T>(const PQRDesc*, int, PQRState*, int, hipStream_t);
 
 SPAQR_PQR_INST(double)

@@ -185,7 +185,7 @@ struct PQRDesc {
   double noise;
   int m, n, forced;
   int blk0, nblk;    // this matrix's column chunks in the launch (set by the launcher)
-  int pad_;
+  int cw;            // columns per chunk (PQR_CW; set by the launcher)
 };
 
 // Per-matrix state of the step-synchronous pivoted QR, double-buffered by
@@ -319,7 +319,7 @@ void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPa
                      const int2* bmap, hipStream_t s);
 template <typename T>
 void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRState* states,
-                     PQRPart* parts, const int2* bmap, int* active, int i, double eps, int max_m,
+                     PQRPart* parts, const int2* bmap, int* active, int i, double eps, int max_m, int cw,
                      hipStream_t s);
 template <typename T>
 void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int steps, hipStream_t s);
