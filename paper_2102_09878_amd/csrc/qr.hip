@@ -17,6 +17,7 @@
 // Trailing update C <- (I - V T V^T)^T C over (front, 64-column tile, row
 // segment) blocks: W_s = V_s^T C_s per segment, W = T^T sum_s W_s, then
 // C_s -= V_s W.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "spaqr_impl.h"
@@ -379,6 +380,176 @@ __global__ __launch_bounds__(PBS) void k_qr_panel_reg(const QRDesc* __restrict__
   }
   double* Tg = tbuf + (int64_t)blockIdx.x * NB * NB;
   for (int e = tid; e < NB * NB; e += PBS) Tg[e] = Ts[e / NB][e % NB];
+}
+
+// ---------------------------------------------------------------------------
+// panel of tall FP32 fronts, one cooperative launch per panel
+//
+// Work-group (f, s) holds rows j0 + s TSEG .. + TSEG of front f in registers
+// (same ownership as the register panel above).  Each column step needs two
+// sums over all row segments of the front - ||tail||^2 and the kb-1 dot
+// products - exchanged through small global buffers across two grid
+// barriers.  The step loop runs to the largest panel width of the launch in
+// every work-group, so all of them reach every barrier.
+// ---------------------------------------------------------------------------
+constexpr int TSEG = PBS * PRPT;
+
+struct CoopShared {
+  double sh[8];
+  double red[8][NB];
+  double sv[NB];
+  double gcol[NB];
+  double fj[NB];
+  double rowc[NB];
+  double Ts[NB][NB + 1];
+};
+
+template <int I>
+__device__ __forceinline__ void coop_step(float (&P)[PRPT][NB], int j0, int m, int kb, int rbase, int sg, int S,
+                                          float* tau, double* normp, double* dp, double* rowc_g, CoopShared& L) {
+  namespace cg = cooperative_groups;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const bool work = I < kb;
+  const int c = j0 + I;
+  double* rowc_i = rowc_g + (I & 1) * NB;
+  // phase 1: segment partial of ||A[c+1:, c]||^2; row c lives in segment 0, thread I, slot 0
+  double part = 0.0;
+  if (work) {
+#pragma unroll
+    for (int k = 0; k < PRPT; ++k) {
+      const int r = rbase + tid + PBS * k;
+      if (r > c && r < m) part += (double)P[k][I] * (double)P[k][I];
+    }
+    if (sg == 0 && tid == I)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) rowc_i[q] = P[0][q];
+  }
+  part = block_sum8(part, L.sh);
+  if (work && tid == 0) normp[sg] = part;
+  cg::this_grid().sync();
+  // phase 2: reflector scalars (identical in every segment), scale, dot partials
+  double beta = 0.0, tv = 0.0, scal = 1.0;
+  if (work) {
+    double xn2 = 0.0;
+    for (int t = 0; t < S; ++t) xn2 += normp[t];
+    if (tid < NB) L.rowc[tid] = rowc_i[tid];
+    __syncthreads();
+    house_scalars(L.rowc[I], xn2, beta, tv, scal);
+    float acc[NB - 1];
+#pragma unroll
+    for (int q = 0; q < NB - 1; ++q) acc[q] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PRPT; ++k) {
+      const int r = rbase + tid + PBS * k;
+      if (r <= c || r >= m) continue;
+      if (tv != 0.0) P[k][I] = static_cast<float>(P[k][I] * scal);
+      const float vi = P[k][I];
+#pragma unroll
+      for (int q = 0; q < NB - 1; ++q) acc[q] = fmaf(vi, P[k][q < I ? q : q + 1], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NB - 1; ++q) {
+      const double w = wave_sum((double)acc[q]);
+      if (lane == 0) L.red[wv][q] = w;
+    }
+    __syncthreads();
+    if (tid < kb - 1)
+      dp[sg * NB + tid] = ((L.red[0][tid] + L.red[1][tid]) + (L.red[2][tid] + L.red[3][tid])) +
+                          ((L.red[4][tid] + L.red[5][tid]) + (L.red[6][tid] + L.red[7][tid]));
+  }
+  cg::this_grid().sync();
+  // phase 3: sums over the segments, T column, update of the owned rows
+  if (work) {
+    const double tvT = (double)static_cast<float>(tv);
+    if (tid < kb - 1) {
+      double a = 0.0;
+      for (int t = 0; t < S; ++t) a += dp[t * NB + tid];
+      L.sv[tid] = a;
+    }
+    __syncthreads();
+    if (tid < kb - 1) {
+      if (tid < I)
+        L.gcol[tid] = L.sv[tid] + L.rowc[tid];
+      else
+        L.fj[tid + 1] = tv * (L.sv[tid] + L.rowc[tid + 1]);
+    }
+    __syncthreads();
+    if (tid < I) {
+      double a2 = 0.0;
+      for (int b2 = tid; b2 < I; ++b2) a2 += L.Ts[tid][b2] * L.gcol[b2];
+      L.Ts[tid][I] = -tvT * a2;
+    } else if (tid == I) {
+      L.Ts[I][I] = tvT;
+    }
+#pragma unroll
+    for (int k = 0; k < PRPT; ++k) {
+      const int r = rbase + tid + PBS * k;
+      if (r < c || r >= m) continue;
+      const double vi = P[k][I];
+      if (r == c) {
+#pragma unroll
+        for (int q = I + 1; q < NB; ++q)
+          if (q < kb && tv != 0.0) P[k][q] = static_cast<float>((double)P[k][q] - L.fj[q]);
+        P[k][I] = static_cast<float>(beta);
+      } else if (tv != 0.0) {
+#pragma unroll
+        for (int q = I + 1; q < NB; ++q)
+          if (q < kb) P[k][q] = static_cast<float>((double)P[k][q] - L.fj[q] * vi);
+      }
+    }
+    if (sg == 0 && tid == 0) tau[c] = static_cast<float>(tv);
+  }
+  __syncthreads();
+}
+
+// kbmax is the same in every work-group, so every one runs the same steps
+// and reaches every grid barrier.
+template <int I>
+__device__ __forceinline__ void coop_steps(float (&P)[PRPT][NB], int j0, int m, int kb, int kbmax, int rbase, int sg,
+                                           int S, float* tau, double* normp, double* dp, double* rowc_g,
+                                           CoopShared& L) {
+  if constexpr (I < NB) {
+    if (I >= kbmax) return;
+    coop_step<I>(P, j0, m, kb, rbase, sg, S, tau, normp, dp, rowc_g, L);
+    coop_steps<I + 1>(P, j0, m, kb, kbmax, rbase, sg, S, tau, normp, dp, rowc_g, L);
+  }
+}
+
+__global__ __launch_bounds__(PBS) void k_qrp_coop(const QRDesc* __restrict__ D, int j0, int kbmax, int S,
+                                                  QRWork ws) {
+  const int f = blockIdx.x / S, sg = blockIdx.x % S;
+  const QRDesc d = D[f];
+  const int kk = min(d.m, d.k);
+  const int kb = j0 < kk ? min(NB, kk - j0) : 0;
+  float* A = static_cast<float*>(d.A);
+  const int64_t lda = d.lda;
+  const int m = d.m;
+  const int tid = threadIdx.x;
+  const int rbase = j0 + sg * TSEG;
+  __shared__ CoopShared L;
+  float P[PRPT][NB];
+#pragma unroll
+  for (int k = 0; k < PRPT; ++k) {
+    const int r = rbase + tid + PBS * k;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) P[k][q] = (r < m && q < kb) ? A[r + (int64_t)(j0 + q) * lda] : 0.0f;
+  }
+  for (int e = tid; e < NB * NB; e += PBS) L.Ts[e / NB][e % NB] = 0.0;
+  __syncthreads();
+  coop_steps<0>(P, j0, m, kb, kbmax, rbase, sg, S, static_cast<float*>(d.tau), ws.normp + (int64_t)f * ws.MS,
+                ws.dp + (int64_t)f * ws.MS * NB, ws.gp + (int64_t)f * ws.MS * NB * NB, L);
+#pragma unroll
+  for (int k = 0; k < PRPT; ++k) {
+    const int r = rbase + tid + PBS * k;
+    if (r < m)
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        if (q < kb) A[r + (int64_t)(j0 + q) * lda] = P[k][q];
+  }
+  if (sg == 0 && kb > 0) {
+    double* Tg = ws.tbuf + (int64_t)f * NB * NB;
+    for (int e = tid; e < NB * NB; e += PBS) Tg[e] = L.Ts[e / NB][e % NB];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -823,7 +994,27 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork&
       if (rest > 0) tiles = std::max(tiles, (rest + TN - 1) / TN);
       segs = std::max(segs, (d.m + RS - 1) / RS);
     }
-    if (split) {
+    int coop_segs = 0;
+    if (split && sizeof(T) == 4) {
+      coop_segs = (mmax - j0 + TSEG - 1) / TSEG;
+      static int max_coop = -1;
+      if (max_coop < 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        SPAQR_HIP(hipGetDevice(&dev));
+        SPAQR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        SPAQR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_qrp_coop, PBS, 0));
+        max_coop = per_cu * cus;
+      }
+      if ((int64_t)nf * coop_segs > max_coop || coop_segs > ws.MS) coop_segs = 0;
+    }
+    if (coop_segs > 0) {
+      const QRDesc* dd = d_desc;
+      int a_j0 = j0, a_kb = kbmax, a_s = coop_segs;
+      QRWork a_ws = ws;
+      void* args[] = {(void*)&dd, (void*)&a_j0, (void*)&a_kb, (void*)&a_s, (void*)&a_ws};
+      SPAQR_HIP(hipLaunchCooperativeKernel((const void*)k_qrp_coop, dim3(nf * coop_segs), dim3(PBS), args, 0, s));
+      ++*launches;
+    } else if (split) {
       const dim3 g(nf, segs);
       for (int i = 0; i <= kbmax; ++i) {
         hipLaunchKernelGGL(k_qrp_a<T>, g, dim3(BS), 0, s, d_desc, j0, i, ws);
