@@ -10,9 +10,13 @@ HBM.  Both precision forms are measured (FP64 fronts/factors, and FP32
 fronts/factors with FP64 CGLS); the faster one is reported as `value`.
 
 Prints ONE JSON line.  `roofline` describes the dominant kernel (one pivot
-step of the batched rank-revealing QRs), timed live with HIP events on the
-library stream over the timed region (every --every-th launch);
-`cpu_baseline` times the FP64 CPU oracle on a bounded sample.
+step of the batched rank-revealing QRs), timed live over the timed region
+(every --every-th launch): the timed launches stamp their own start and end
+with the GPU's constant-rate clock, so `avg_launch_us` is the kernel
+duration a profiler reports (no launch gaps).  `traffic` comes from the
+counter profile in profiles/ while the kernel source is unchanged since it
+was taken, else null.  `cpu_baseline` times the FP64 CPU oracle on a
+bounded sample.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1]
 """
@@ -30,6 +34,22 @@ sys.path.insert(0, ROOT)
 
 METRIC = "factor+CGLS time to 1e-10 residual (s) at 256² grid; factor HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+
+
+def _counter_traffic(kernel_src: str):
+    """Measured HBM bytes per launch of the dominant kernel (FETCH_SIZE +
+    WRITE_SIZE, copy-calibrated) from profiles/, if the kernel source still
+    has the hash recorded with the counters; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_k_pqr_step.json")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(os.path.join(ROOT, kernel_src), "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def _cpu_baseline(seconds_budget: float, target_flops: float) -> dict:
@@ -110,7 +130,19 @@ def main() -> int:
     ap.add_argument("--every", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch form")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run one plain device copy of MIB MiB (calibrates HBM traffic counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}))
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this "
               "path is a design note, not built", file=sys.stderr)
@@ -165,7 +197,9 @@ def main() -> int:
     if kern["calls"] and kern["seconds"] > 0:
         achieved = kern["bytes"] / kern["seconds"] / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": _counter_traffic("paper_2102_09878_amd/csrc/pqr.hip"),
+                    "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                     "kernel": f"k_pqr_step<{'float' if best == 'fp32' else 'double'}>",
                     "avg_launch_us": kern["seconds"] / kern["calls"] * 1e6,
                     "bytes_per_launch": kern["bytes"] / kern["calls"], "timed_launches": kern["calls"]}

@@ -438,12 +438,9 @@ class Factorizer {
     timed_steps_.clear();
     while (steps < kmax) {
       const bool timed = H.kt.pick("pqr_step");
-      if (timed) {
-        H.kt.mark(st);
-        timed_steps_.push_back(steps);
-      }
-      launch_pqr_step<T>(d, total, total, states, parts, dmap, active, steps, eps_, max_m, cw, st);
-      if (timed) H.kt.mark(st);
+      unsigned long long* stamp = timed ? H.kt.stamp(st) : nullptr;
+      if (timed) timed_steps_.push_back(steps);
+      launch_pqr_step<T>(d, total, total, states, parts, dmap, active, steps, eps_, max_m, cw, stamp, st);
       ++launches_;
       ++steps;
       if (steps % 16 == 0 && steps < kmax) {

@@ -2,6 +2,7 @@
 // matrix, the factor (device ops + host metadata) and solver workspace.
 #pragma once
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -40,7 +41,12 @@ struct ApplyBatch {
   double flops = 0.0;
 };
 
-// Opt-in per-launch timing of one kernel family with HIP events.
+// Opt-in per-launch timing of one kernel family.  Families whose kernels
+// stamp themselves ("pqr_step") record, per timed launch, the earliest
+// work-group start and the latest work-group end read from the GPU's
+// constant-rate real-time counter (the kernel's own duration, as a profiler
+// reports it); the others are bracketed with HIP events (which also count
+// the launch gap).
 struct KernelTimer {
   std::string family;
   std::vector<hipEvent_t> pool;
@@ -48,6 +54,10 @@ struct KernelTimer {
   int64_t calls = 0, seen = 0;
   int every = 1;
   double seconds = 0.0, bytes = 0.0, flops = 0.0;
+  // device stamps: STAMP_SLOTS x STAMP_STRIDE words per timed launch
+  unsigned long long* d_stamp = nullptr;
+  size_t stamp_cap = 0, stamp_used = 0;
+  double clock_hz = 0.0;
 
   bool on(const char* f) const { return !family.empty() && family == f; }
   // true for the launches that are timed (every `every`-th one of the family)
@@ -60,8 +70,60 @@ struct KernelTimer {
     }
     SPAQR_HIP(hipEventRecord(pool[used++], s));
   }
+
+  // Slot for the next timed launch.  Slots start at zero; a kernel folds
+  // ~start and end into them with atomicMax, so no per-launch reset is
+  // needed (the buffer is cleared when it is created and after a harvest).
+  unsigned long long* stamp(hipStream_t s) {
+    const size_t per = (size_t)STAMP_SLOTS * STAMP_STRIDE;
+    if (stamp_used == stamp_cap) {
+      const size_t cap = std::max<size_t>(2048, 2 * stamp_cap);
+      unsigned long long* n = nullptr;
+      SPAQR_HIP(hipMalloc(&n, cap * per * sizeof(unsigned long long)));
+      SPAQR_HIP(hipMemsetAsync(n, 0, cap * per * sizeof(unsigned long long), s));
+      if (d_stamp) {
+        SPAQR_HIP(hipMemcpyAsync(n, d_stamp, stamp_used * per * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToDevice, s));
+        SPAQR_HIP(hipStreamSynchronize(s));
+        SPAQR_HIP(hipFree(d_stamp));
+      }
+      d_stamp = n;
+      stamp_cap = cap;
+      stamp_stream = s;
+    }
+    return d_stamp + per * stamp_used++;
+  }
+  hipStream_t stamp_stream = nullptr;
+  void harvest_stamps() {
+    if (!stamp_used) return;
+    if (clock_hz == 0.0) {
+      int dev = 0, khz = 0;
+      SPAQR_HIP(hipGetDevice(&dev));
+      SPAQR_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+      clock_hz = khz * 1e3;
+    }
+    const size_t per = (size_t)STAMP_SLOTS * STAMP_STRIDE;
+    std::vector<unsigned long long> h(per * stamp_used);
+    SPAQR_HIP(hipMemcpy(h.data(), d_stamp, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < stamp_used; ++k) {
+      unsigned long long t0 = ~0ull, t1 = 0;
+      for (int sl = 0; sl < STAMP_SLOTS; ++sl) {
+        const unsigned long long* e = h.data() + per * k + (size_t)sl * STAMP_STRIDE;
+        if (e[0] == 0) continue;  // no work-group used this slot
+        t0 = std::min(t0, ~e[0]);
+        t1 = std::max(t1, e[1]);
+      }
+      if (t0 != ~0ull && t1 >= t0) {
+        seconds += (double)(t1 - t0) / clock_hz;
+        ++calls;
+      }
+    }
+    SPAQR_HIP(hipMemsetAsync(d_stamp, 0, h.size() * sizeof(unsigned long long), stamp_stream));
+    stamp_used = 0;
+  }
   // call after the stream has been synchronised
   void harvest() {
+    harvest_stamps();
     for (size_t i = 0; i + 1 < used; i += 2) {
       float ms = 0.f;
       SPAQR_HIP(hipEventElapsedTime(&ms, pool[i], pool[i + 1]));
@@ -74,12 +136,16 @@ struct KernelTimer {
     family = f ? f : "";
     every = ev > 0 ? ev : 1;
     used = 0;
+    if (d_stamp)
+      SPAQR_HIP(hipMemset(d_stamp, 0, stamp_cap * STAMP_SLOTS * STAMP_STRIDE * sizeof(unsigned long long)));
+    stamp_used = 0;
     calls = 0;
     seen = 0;
     seconds = bytes = flops = 0.0;
   }
   ~KernelTimer() {
     for (auto e : pool) (void)hipEventDestroy(e);
+    if (d_stamp) (void)hipFree(d_stamp);
   }
 };
 

@@ -145,11 +145,28 @@ __global__ __launch_bounds__(BS) void k_pqr_init(const PQRDesc* __restrict__ D,
 // launcher picks 2 or 4 when that covers the batch's tallest matrix; 0
 // keeps the columns in memory, which measured faster for taller ones).
 // NC = cw / 4 columns per wave.
+// Optional self-timing: when stamp is set, thread 0 of every work-group
+// folds the complement of the real-time counter into its slot's first word
+// on entry (so the maximum is the earliest start) and the counter into the
+// second word on exit.  Work-groups spread over STAMP_SLOTS slots, one
+// 64-byte line apart, to keep the atomics from queueing on one address.
+struct StampScope {
+  unsigned long long* p;
+  __device__ explicit StampScope(unsigned long long* q)
+      : p(q ? q + (blockIdx.x % STAMP_SLOTS) * STAMP_STRIDE : nullptr) {
+    if (p && threadIdx.x == 0) atomicMax(p, ~(unsigned long long)__builtin_amdgcn_s_memrealtime());
+  }
+  __device__ ~StampScope() {
+    if (p && threadIdx.x == 0) atomicMax(p + 1, (unsigned long long)__builtin_amdgcn_s_memrealtime());
+  }
+};
+
 template <typename T, int PQ, int NC>
 __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, PQRState* __restrict__ S,
                                                  PQRPart* __restrict__ parts, int total_parts,
                                                  const int2* __restrict__ bmap, int* __restrict__ active,
-                                                 int i, double eps) {
+                                                 int i, double eps, unsigned long long* stamp) {
+  const StampScope timing(stamp);
   extern __shared__ double x[];  // pivot column rows i..m-1
   __shared__ double sh[4];
   __shared__ double shv[4];
@@ -411,14 +428,14 @@ void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPa
 template <typename T>
 void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRState* states,
                      PQRPart* parts, const int2* bmap, int* active, int i, double eps, int max_m, int cw,
-                     hipStream_t s) {
+                     unsigned long long* stamp, hipStream_t s) {
   if (nblocks <= 0) return;
   const size_t lds = (size_t)std::max(1, max_m) * sizeof(double);
   if (lds > 64 * 1024) throw Error(SPAQR_EARG, "rank-revealing QR block taller than 8192 rows");
   const int rows = max_m - i;
 #define SPAQR_PQR_GO(Q, C)                                                                                   \
   hipLaunchKernelGGL((k_pqr_step<T, Q, C>), dim3(nblocks), dim3(BS), lds, s, d_desc, states, parts, total_parts, \
-                     bmap, active, i, eps)
+                     bmap, active, i, eps, stamp)
   if (cw == PQR_CW) {
     if (rows <= 128)
       SPAQR_PQR_GO(2, PQR_CW / 4);
@@ -443,7 +460,7 @@ void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int st
 #define SPAQR_PQR_INST(T)                                                                             \
   template void launch_pqr_init<T>(const PQRDesc*, int, PQRState*, PQRPart*, const int2*, hipStream_t); \
   template void launch_pqr_step<T>(const PQRDesc*, int, int, PQRState*, PQRPart*, const int2*, int*, int, \
-                                   double, int, int, hipStream_t);                                    \
+                                   double, int, int, unsigned long long*, hipStream_t);               \
   template void launch_pqr_finish<T>(const PQRDesc*, int, PQRState*, int, hipStream_t);
 
 SPAQR_PQR_INST(double)

@@ -20,6 +20,8 @@
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "spaqr_impl.h"
 
 namespace spaqr {
@@ -995,7 +997,10 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork&
       segs = std::max(segs, (d.m + RS - 1) / RS);
     }
     int coop_segs = 0;
-    if (split && sizeof(T) == 4) {
+    // SPAQR_NO_COOP=1 keeps tall panels on the two-launches-per-column path
+    // (for tools that cannot follow cooperative launches)
+    static const bool no_coop = std::getenv("SPAQR_NO_COOP") != nullptr;
+    if (split && sizeof(T) == 4 && !no_coop) {
       coop_segs = (mmax - j0 + TSEG - 1) / TSEG;
       static int max_coop = -1;
       if (max_coop < 0) {
