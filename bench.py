@@ -165,6 +165,7 @@ def main() -> int:
             s.cgls(b, tol=1e-10)
         s.time_kernel(args.family, args.every)
         f_sec, c_sec, iters, res = 0.0, 0.0, [], []
+        phase = {}
         fac_bytes = 0.0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -173,6 +174,8 @@ def main() -> int:
             st = s.stats()
             x, info = s.cgls(b, tol=1e-10)
             f_sec += st["factor_seconds"]
+            for k, v in st["phase_seconds"].items():
+                phase[k] = phase.get(k, 0.0) + v / args.steps
             c_sec += info["seconds"]
             fac_bytes += sum(st["bytes"].values())
             iters.append(info["iters"])
@@ -183,7 +186,7 @@ def main() -> int:
         ok = all(r <= 1e-10 for r in res)
         forms[form] = dict(
             s_per_step=(t1 - t0) / args.steps, factor_s=f_sec / args.steps, cgls_s=c_sec / args.steps,
-            cgls_iters=iters[-1], residual=max(res), converged=ok,
+            cgls_iters=iters[-1], residual=max(res), converged=ok, phase_gpu_s=phase,
             factor_gbs=fac_bytes / f_sec / 1e9 if f_sec > 0 else None,
             factor_flops=sum(st["flops"].values()), mem_factor=st["mem_factor"],
             kernel=dict(calls=st["kernel_calls"], seconds=st["kernel_seconds"], bytes=st["kernel_bytes"],

@@ -919,7 +919,7 @@ void Factorizer<T>::scale_all() {
   IntPool tp;
   std::vector<TrsmDesc> td;
   std::vector<size_t> td_map;
-  int td_rows = 0;
+  int td_rows = 0, td_c = 0;
   for (int g : live_groups()) {
     RG& gr = G[g];
     for (int q : gr.clus) {
@@ -934,13 +934,14 @@ void Factorizer<T>::scale_all() {
       td_map.push_back(tp.add(colmap(gr, C[q].slots, true)));
       td.push_back(d);
       td_rows = std::max(td_rows, d.nrows);
+      td_c = std::max(td_c, d.c);
       flops_[PH_SCALE] += (double)gr.nrows * d.c * d.c;
       bytes_[PH_SCALE] += 2.0 * sizeof(T) * gr.nrows * d.c;
     }
   }
   int* dtp = upload(tp.v);
   for (size_t i = 0; i < td.size(); ++i) td[i].colmap = dtp + td_map[i];
-  launch_trsm<T>(upload(td), (int)td.size(), td_rows, st);
+  launch_trsm<T>(upload(td), (int)td.size(), td_rows, td_c, st);
   ++launches_;
   timer_end();
   // rank-deficiency flags are read together with the step-1 ranks

@@ -144,6 +144,61 @@ __global__ __launch_bounds__(BS) void k_trsm(const TrsmDesc* __restrict__ D) {
   }
 }
 
+// Same solve with the work-group's 64 rows of B held in LDS (FP64) while
+// they are solved: B is read and written once, the left-looking updates
+// read the solved columns from LDS, and the current 16-column block of R is
+// staged in LDS.  One wave per work-group, thread = row.  Dynamic LDS:
+// c (64 + 1 + TRSM_NB) doubles for the largest c of the launch.
+constexpr int TRSM_ROWS = 64;
+
+template <typename T>
+__global__ __launch_bounds__(TRSM_ROWS) void k_trsm_lds(const TrsmDesc* __restrict__ D, int cmax) {
+  extern __shared__ double lds[];
+  const TrsmDesc d = D[blockIdx.x];
+  if ((int)blockIdx.y * TRSM_ROWS >= d.nrows) return;  // whole block
+  double* Xs = lds;                                        // [c][TRSM_ROWS + 1]
+  double* Rs = lds + (size_t)cmax * (TRSM_ROWS + 1);       // [c][TRSM_NB]
+  const int lane = threadIdx.x;
+  const int r = blockIdx.y * TRSM_ROWS + lane;
+  const bool live = r < d.nrows;
+  T* B = static_cast<T*>(d.B);
+  const T* R = static_cast<const T*>(d.R);
+  const int c = d.c;
+  for (int j = 0; j < c; ++j)
+    Xs[j * (TRSM_ROWS + 1) + lane] = live ? (double)B[r + (int64_t)d.colmap[j] * d.ldb] : 0.0;
+  for (int jb = 0; jb < c; jb += TRSM_NB) {
+    const int nb = min(TRSM_NB, c - jb);
+    __syncthreads();
+    for (int e = lane; e < (jb + nb) * TRSM_NB; e += TRSM_ROWS) {
+      const int i = e / TRSM_NB, k = e % TRSM_NB;
+      Rs[e] = k < nb ? (double)R[i + (int64_t)(jb + k) * d.ldr] : 0.0;
+    }
+    __syncthreads();
+    double acc[TRSM_NB];
+#pragma unroll
+    for (int k = 0; k < TRSM_NB; ++k) acc[k] = k < nb ? Xs[(jb + k) * (TRSM_ROWS + 1) + lane] : 0.0;
+    for (int i = 0; i < jb; ++i) {
+      const double bi = Xs[i * (TRSM_ROWS + 1) + lane];
+#pragma unroll
+      for (int k = 0; k < TRSM_NB; ++k) acc[k] -= bi * Rs[i * TRSM_NB + k];
+    }
+#pragma unroll
+    for (int k = 0; k < TRSM_NB; ++k) {
+      if (k < nb) {
+        acc[k] /= Rs[(jb + k) * TRSM_NB + k];
+#pragma unroll
+        for (int k2 = k + 1; k2 < TRSM_NB; ++k2)
+          if (k2 < nb) acc[k2] -= acc[k] * Rs[(jb + k) * TRSM_NB + k2];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < TRSM_NB; ++k)
+      if (k < nb) Xs[(jb + k) * (TRSM_ROWS + 1) + lane] = acc[k];
+  }
+  if (live)
+    for (int j = 0; j < c; ++j) B[r + (int64_t)d.colmap[j] * d.ldb] = static_cast<T>(Xs[j * (TRSM_ROWS + 1) + lane]);
+}
+
 // owner of each row: cluster with the largest sum of squared entries, the
 // first (lowest) cluster on ties.  A work-group covers 64 rows (one per
 // lane, coalesced column reads); its 4 waves take every 4th cluster and
@@ -271,9 +326,21 @@ void launch_scatter_csr(T* base, const int64_t* dst, const double* ahat, int64_t
 }
 
 template <typename T>
-void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, hipStream_t s) {
+void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, int max_c, hipStream_t s) {
   if (n <= 0 || max_rows <= 0) return;
-  hipLaunchKernelGGL(k_trsm<T>, dim3(n, (max_rows + BS - 1) / BS), dim3(BS), 0, s, d_desc);
+  static int lds_cap = -1;
+  if (lds_cap < 0) {
+    int dev = 0;
+    SPAQR_HIP(hipGetDevice(&dev));
+    SPAQR_HIP(hipDeviceGetAttribute(&lds_cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  }
+  const size_t lds = (size_t)max_c * (TRSM_ROWS + 1 + TRSM_NB) * sizeof(double);
+  if (max_c > 0 && lds <= (size_t)lds_cap) {
+    hipLaunchKernelGGL(k_trsm_lds<T>, dim3(n, (max_rows + TRSM_ROWS - 1) / TRSM_ROWS), dim3(TRSM_ROWS), lds, s,
+                       d_desc, max_c);
+  } else {
+    hipLaunchKernelGGL(k_trsm<T>, dim3(n, (max_rows + BS - 1) / BS), dim3(BS), 0, s, d_desc);
+  }
   SPAQR_HIP(hipGetLastError());
 }
 
@@ -309,7 +376,7 @@ void launch_scatter(const ScatterDesc* d_desc, int n, hipStream_t s) {
 #define SPAQR_INST(T)                                                                          \
   template void launch_gather<T>(const GatherDesc*, int, int, hipStream_t);                    \
   template void launch_scatter_csr<T>(T*, const int64_t*, const double*, int64_t, hipStream_t); \
-  template void launch_trsm<T>(const TrsmDesc*, int, int, hipStream_t);                             \
+  template void launch_trsm<T>(const TrsmDesc*, int, int, int, hipStream_t);                        \
   template void launch_owner<T>(const OwnerDesc*, int, int, hipStream_t);                           \
   template void launch_rowcopy<T>(const RowCopyDesc*, int, int, hipStream_t);                         \
   template void launch_extract<T>(const ExtractDesc*, int, hipStream_t);                       \

@@ -328,7 +328,7 @@ void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRSta
 template <typename T>
 void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int steps, hipStream_t s);
 template <typename T>
-void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, hipStream_t s);
+void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, int max_c, hipStream_t s);
 template <typename T>
 void launch_owner(const OwnerDesc* d_desc, int n, int max_rows, hipStream_t s);
 template <typename T>
