@@ -877,19 +877,36 @@ __global__ __launch_bounds__(BS) void k_qru_w_mfma(const QRDesc* __restrict__ D,
   const int ab = wv & 1, jb = 2 * (wv >> 1);
   const int li = lane & 15, lk = lane >> 4;
   f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  // the next 64-row slab is fetched into registers while the current one
+  // is multiplied out of LDS
+  float vr[64 * NB / BS], cr[64 * TN / BS];
+  auto fetch = [&](int rb) {
+#pragma unroll
+    for (int u = 0; u < 64 * NB / BS; ++u) {
+      const int e = tid + u * BS, rr = e & 63, a = e >> 6, r = rb + rr;
+      vr[u] = r < r1 ? vref(A, lda, j0, a, kb, r) : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 64 * TN / BS; ++u) {
+      const int e = tid + u * BS, rr = e & 63, cc = e >> 6, r = rb + rr;
+      cr[u] = (r < r1 && cc < nc) ? A[r + (int64_t)(c0 + cc) * lda] : 0.0f;
+    }
+  };
+  fetch(r0);
   for (int rb = r0; rb < r1; rb += 64) {
     __syncthreads();
-    for (int e = tid; e < 64 * NB; e += BS) {
-      const int rr = e & 63, a = e >> 6;
-      const int r = rb + rr;
-      Vs[rr][a] = r < r1 ? vref(A, lda, j0, a, kb, r) : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 64 * NB / BS; ++u) {
+      const int e = tid + u * BS;
+      Vs[e & 63][e >> 6] = vr[u];
     }
-    for (int e = tid; e < 64 * TN; e += BS) {
-      const int rr = e & 63, cc = e >> 6;
-      const int r = rb + rr;
-      Cs[rr][cc] = (r < r1 && cc < nc) ? A[r + (int64_t)(c0 + cc) * lda] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 64 * TN / BS; ++u) {
+      const int e = tid + u * BS;
+      Cs[e & 63][e >> 6] = cr[u];
     }
     __syncthreads();
+    if (rb + 64 < r1) fetch(rb + 64);
 #pragma unroll
     for (int k4 = 0; k4 < 16; ++k4) {
       const int rr = 4 * k4 + lk;
@@ -932,14 +949,38 @@ __global__ __launch_bounds__(BS) void k_qru_apply_mfma(const QRDesc* __restrict_
   for (int e = tid; e < NB * TN; e += BS) Ws[e / TN][e % TN] = (float)win[e];
   const int li = lane & 15, lk = lane >> 4;
   const int col = 16 * wv + 4 * lk;  // first of this lane's four columns
+  // The next slab's reflector rows and this lane's 16 entries of C are
+  // fetched into registers while the current slab is multiplied.
+  float vr[64 * NB / BS], cr[4][4];
+  auto fetch = [&](int rb) {
+#pragma unroll
+    for (int u = 0; u < 64 * NB / BS; ++u) {
+      const int e = tid + u * BS, rr = e & 63, a = e >> 6, r = rb + rr;
+      vr[u] = r < r1 ? vref(A, lda, j0, a, kb, r) : 0.0f;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = rb + 16 * b + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        cr[b][v] = (r < r1 && col + v < nc) ? A[r + (int64_t)(c0 + col + v) * lda] : 0.0f;
+    }
+  };
+  fetch(r0);
   for (int rb = r0; rb < r1; rb += 64) {
     __syncthreads();
-    for (int e = tid; e < 64 * NB; e += BS) {
-      const int rr = e & 63, a = e >> 6;
-      const int r = rb + rr;
-      Vs[rr][a] = r < r1 ? vref(A, lda, j0, a, kb, r) : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 64 * NB / BS; ++u) {
+      const int e = tid + u * BS;
+      Vs[e & 63][e >> 6] = vr[u];
     }
+    float cc[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cc[b][v] = cr[b][v];
     __syncthreads();
+    if (rb + 64 < r1) fetch(rb + 64);
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -952,10 +993,7 @@ __global__ __launch_bounds__(BS) void k_qru_apply_mfma(const QRDesc* __restrict_
       if (r < r1)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          if (col + v < nc) {
-            float* p = A + r + (int64_t)(c0 + col + v) * lda;
-            *p = *p - acc[v];
-          }
+          if (col + v < nc) A[r + (int64_t)(c0 + col + v) * lda] = cc[b][v] - acc[v];
     }
   }
 }
