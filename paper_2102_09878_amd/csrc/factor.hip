@@ -105,8 +105,9 @@ void Handle::release_device() {
   (void)hipStreamSynchronize(stream);
   for (void* p : {(void*)d_ahat, (void*)d_rp, (void*)d_ci, (void*)d_ahatT, (void*)d_atp, (void*)d_ati,
                   (void*)d_init_dst, (void*)d_D, (void*)d_cg, (void*)d_vals, (void*)d_atsrc, (void*)d_flag,
-                  (void*)d_segc, (void*)d_segr, (void*)d_act})
+                  (void*)d_segc, (void*)d_segr, (void*)d_act, (void*)d_pqr_err})
     if (p) (void)hipFree(p);
+  d_pqr_err = nullptr;
   if (h_sc) (void)hipHostFree(h_sc);
   if (h_act) (void)hipHostFree(h_act);
   d_segc = d_segr = nullptr;
@@ -156,6 +157,7 @@ void Handle::ensure_device() {
   d_segc = dcopy(P.seg_col, plan_bytes);
   d_segr = dcopy(P.seg_row, plan_bytes);
   d_act = dcopy(std::vector<int>(P.count, 1), plan_bytes);
+  d_pqr_err = dcopy(std::vector<int>(1), plan_bytes);
   SPAQR_HIP(hipHostMalloc((void**)&h_sc, (P.count * 8 + 64) * sizeof(double), hipHostMallocDefault));
   SPAQR_HIP(hipHostMalloc((void**)&h_act, P.count * sizeof(int), hipHostMallocDefault));
   dev_ready = true;
@@ -406,12 +408,89 @@ class Factorizer {
   }
   std::vector<int> timed_steps_;
 
+  // After a sync: a persistent pivoted QR that abandoned a wait left ranks of
+  // 0 and partial factors; report it.
+  // (fetch_pqr_err queues the copy of the flag ahead of that sync)
+  int* pqr_err_h_ = nullptr;
+  void fetch_pqr_err() {
+    if (!pqr_err_h_) pqr_err_h_ = static_cast<int*>(H.stage.alloc(sizeof(int)));
+    SPAQR_HIP(hipMemcpyAsync(pqr_err_h_, H.d_pqr_err, sizeof(int), hipMemcpyDeviceToHost, st));
+  }
+  void check_pqr() {
+    if (pqr_err_h_ && *pqr_err_h_) {
+      *pqr_err_h_ = 0;
+      SPAQR_HIP(hipMemset(H.d_pqr_err, 0, sizeof(int)));
+      throw Error(SPAQR_EHIP, "pivoted QR: a work-group exchange wait exceeded its limit");
+    }
+  }
+
+  // Batched rank-revealing QR in one cooperative launch, when the batch
+  // qualifies (see pqr_run_width); false otherwise.
+  bool run_pqr_persistent(std::vector<PQRDesc>& q, int max_m) {
+    std::vector<int> ns;
+    ns.reserve(q.size());
+    for (const PQRDesc& e : q) ns.push_back(e.n);
+    int rows = 0;
+    const int cw = pqr_run_width<T>(max_m, ns, &rows);
+    if (cw <= 0) return false;
+    int total = 0, groups = 0;
+    std::vector<int2> bmap;
+    for (size_t k = 0; k < q.size(); ++k) {
+      q[k].cw = cw;
+      q[k].blk0 = total;
+      q[k].nblk = std::max(1, (q[k].n + cw - 1) / cw);
+      q[k].g0 = groups;
+      groups += std::max(1, (q[k].n + 7) / 8);
+      for (int c = 0; c < q[k].nblk; ++c) bmap.push_back(make_int2((int)k, c));
+      total += q[k].nblk;
+    }
+    const PQRDesc* d = upload(q);
+    const int2* dmap = upload(bmap);
+    PQRXch xc{};
+    xc.G = total;
+    xc.rows = rows;
+    const size_t words = pqr_xch_words(total, rows, groups, sizeof(T));
+    auto* buf = static_cast<unsigned long long*>(H.arena.alloc(words * sizeof(unsigned long long)));
+    SPAQR_HIP(hipMemsetAsync(buf, 0, words * sizeof(unsigned long long), st));
+    xc.part = buf;
+    xc.pub = buf + 6 * (size_t)total;
+    xc.frop = xc.pub + 2 * (size_t)total * rows * (sizeof(T) / 4);
+    xc.err = H.d_pqr_err;
+    static const bool dbg = std::getenv("SPAQR_DEBUG_PQR") != nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (dbg) {
+      SPAQR_HIP(hipEventCreate(&e0));
+      SPAQR_HIP(hipEventCreate(&e1));
+      SPAQR_HIP(hipEventRecord(e0, st));
+    }
+    launch_pqr_run<T>(d, total, dmap, xc, eps_, cw, nullptr, st);
+    ++launches_;
+    if (dbg) {
+      SPAQR_HIP(hipEventRecord(e1, st));
+      SPAQR_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SPAQR_HIP(hipEventElapsedTime(&ms, e0, e1));
+      int rmax = 0;
+      for (const PQRDesc& e : q) {
+        int r = 0;
+        SPAQR_HIP(hipMemcpy(&r, e.rank_out, sizeof(int), hipMemcpyDeviceToHost));
+        rmax = std::max(rmax, r);
+      }
+      std::fprintf(stderr, "[pqr_run] L%d r%d nmat %zu G %d cw %d rows %d max_m %d steps %d  %.1f us  %.2f us/step\n",
+                   level_, round_, q.size(), total, cw, rows, max_m, rmax, ms * 1e3, ms * 1e3 / std::max(1, rmax + 1));
+      SPAQR_HIP(hipEventDestroy(e0));
+      SPAQR_HIP(hipEventDestroy(e1));
+    }
+    return true;
+  }
+
   // Batched rank-revealing QR: one launch per pivot step until every
   // matrix has stopped (polled every few steps).
   void run_pqr(std::vector<PQRDesc>& q) {
     if (q.empty()) return;
     int total = 0, kmax = 0, max_m = 1, live_m = 0;
     for (const PQRDesc& e : q) max_m = std::max(max_m, e.m);
+    if (run_pqr_persistent(q, max_m)) return;
     // 8-column chunks: wider ones (fewer partials to scan, more columns per
     // wave) measured slower at every matrix height here
     const int cw = PQR_CW;
@@ -432,6 +511,13 @@ class Factorizer {
     auto* parts = static_cast<PQRPart*>(H.arena.alloc(2 * (size_t)total * sizeof(PQRPart)));
     int* active = upload(std::vector<int>{live_m});
     int* h_active = static_cast<int*>(H.stage.alloc(sizeof(int)));
+    static const bool dbg = std::getenv("SPAQR_DEBUG_PQR") != nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (dbg) {
+      SPAQR_HIP(hipEventCreate(&e0));
+      SPAQR_HIP(hipEventCreate(&e1));
+      SPAQR_HIP(hipEventRecord(e0, st));
+    }
     launch_pqr_init<T>(d, total, states, parts, dmap, st);
     ++launches_;
     int steps = 0;
@@ -451,6 +537,16 @@ class Factorizer {
     }
     launch_pqr_finish<T>(d, (int)q.size(), states, steps, st);
     ++launches_;
+    if (dbg) {
+      SPAQR_HIP(hipEventRecord(e1, st));
+      SPAQR_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SPAQR_HIP(hipEventElapsedTime(&ms, e0, e1));
+      std::fprintf(stderr, "[pqr_steps] L%d r%d nmat %zu G %d cw %d max_m %d steps %d  %.1f us  %.2f us/step\n",
+                   level_, round_, q.size(), total, cw, max_m, steps, ms * 1e3, ms * 1e3 / std::max(1, steps));
+      SPAQR_HIP(hipEventDestroy(e0));
+      SPAQR_HIP(hipEventDestroy(e1));
+    }
   }
 
   void run_qr(const std::vector<QRDesc>& q) {
@@ -751,7 +847,9 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
   SPAQR_HIP(hipMemcpyAsync(h_owner, d_owner_all, std::max<size_t>(1, nown) * sizeof(int),
                            hipMemcpyDeviceToHost, st));
   SPAQR_HIP(hipMemcpyAsync(h_rank, d_rank, qe.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+  fetch_pqr_err();
   sync();
+  check_pqr();
   account_pqr(qe, h_rank);
   // new groups, one per (front, owner), appended in front order
   IntPool rp;
@@ -979,7 +1077,9 @@ void Factorizer<T>::step1_all() {
   SPAQR_HIP(hipMemcpyAsync(h, d_rank, nr * sizeof(int), hipMemcpyDeviceToHost, st));
   if (nflags_ > 0)
     SPAQR_HIP(hipMemcpyAsync(h + nr, flags_, nflags_ * sizeof(int), hipMemcpyDeviceToHost, st));
+  fetch_pqr_err();
   sync();
+  check_pqr();
   for (int i = 0; i < nflags_; ++i)
     if (h[nr + i]) throw Error(SPAQR_ERANK, "a scaling block is numerically rank deficient");
   account_pqr(pd, h);
@@ -1136,7 +1236,9 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
   launches_ += 2;
   int* h = static_cast<int*>(H.stage.alloc(std::max<size_t>(1, sel.size()) * sizeof(int)));
   SPAQR_HIP(hipMemcpyAsync(h, d_rank, sel.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+  fetch_pqr_err();
   sync();
+  check_pqr();
   account_pqr(pd, h);
   timer_end();
   for (size_t i = 0; i < ss.size(); ++i) {
@@ -1443,7 +1545,9 @@ void Factorizer<T>::run() {
   if (!live.empty()) throw Error(SPAQR_EARG, "internal: clusters left after the root level");
   if (forced_ && fpos_ != nforced_) throw Error(SPAQR_EARG, "forced rank list not fully used");
   build_apply();
+  fetch_pqr_err();
   sync();
+  check_pqr();
   H.kt.harvest();
   double ph[5] = {0, 0, 0, 0, merge_s};
   for (auto& t : timers_) {

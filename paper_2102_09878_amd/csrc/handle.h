@@ -170,6 +170,7 @@ struct Handle {
   int64_t* d_segc = nullptr;    // problem offsets over columns / rows (count + 1)
   int64_t* d_segr = nullptr;
   int* d_act = nullptr;         // per-problem "still iterating" flags
+  int* d_pqr_err = nullptr;     // persistent pivoted QR: set when a wait was abandoned
   std::vector<double> normA;    // ||A_g||_2 estimate of each problem's current values
   size_t plan_bytes = 0;
   // factor

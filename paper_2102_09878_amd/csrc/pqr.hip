@@ -22,6 +22,7 @@
 
 #include <cfloat>
 #include <climits>
+#include <cstdlib>
 
 #include "spaqr_impl.h"
 
@@ -142,8 +143,9 @@ __global__ __launch_bounds__(BS) void k_pqr_init(const PQRDesc* __restrict__ D,
 }
 
 // PQ: rows per lane held in registers for this work-group's columns (the
-// launcher picks 2 or 4 when that covers the batch's tallest matrix; 0
-// keeps the columns in memory, which measured faster for taller ones).
+// launcher picks 2 to 5 when that covers the batch's tallest matrix from
+// the step's 64-aligned row window; 0 keeps the columns in memory, which
+// measured faster for taller ones).
 // NC = cw / 4 columns per wave.
 // Optional self-timing: when stamp is set, thread 0 of every work-group
 // folds the complement of the real-time counter into its slot's first word
@@ -204,7 +206,12 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
       pval[u] = -1.0, pidx[u] = INT_MAX, pfro[u] = 0.0;
     }
   }
-  const bool regs = PQ > 0 && m - i <= 64 * PQ;
+  // Register rows form a 64-aligned window: lane l holds rows i0 + l + 64 q,
+  // so every per-lane partial sum runs over the rows congruent to l mod 64
+  // in ascending order, whatever the step (the persistent form below keeps
+  // the same grouping and gives bit-identical factors).
+  const int i0 = i & ~63;
+  const bool regs = PQ > 0 && m - i0 <= 64 * PQ;
   int jcol[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) jcol[k] = c0 + wv + 4 * k;
@@ -219,8 +226,8 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
       const T* y = A + (int64_t)j * lda;
 #pragma unroll
       for (int q = 0; q < PQ; ++q) {
-        const int r = i + lane + 64 * q;
-        yv[k][q] = r < m ? (double)y[r] : 0.0;
+        const int r = i0 + lane + 64 * q;
+        yv[k][q] = (r >= i && r < m) ? (double)y[r] : 0.0;
       }
       dnp[k] = done[j];
       v1p[k] = vn1[j];
@@ -323,17 +330,17 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
       if (tv != 0.0)
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
-          const int r = i + lane + 64 * q;
-          if (r < m) dot += x[r - i] * yv[k][q];
+          const int r = i0 + lane + 64 * q;
+          if (r >= i && r < m) dot += x[r - i] * yv[k][q];
         }
       dot = wave_sum(dot);
       const double f = tv * dot;
-      const double yi = __shfl(yv[k][0], 0, 64) - f;
+      const double yi = __shfl(yv[k][0], i - i0, 64) - f;
       if (tv != 0.0)
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
-          const int r = i + lane + 64 * q;
-          if (r < m) {
+          const int r = i0 + lane + 64 * q;
+          if (r >= i && r < m) {
             const T nv = static_cast<T>(yv[k][q] - f * x[r - i]);
             y[r] = nv;
             yv[k][q] = (double)nv;
@@ -350,7 +357,7 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
           double s2 = 0.0;
 #pragma unroll
           for (int q = 0; q < PQ; ++q) {
-            const int r = i + lane + 64 * q;
+            const int r = i0 + lane + 64 * q;
             if (r > i && r < m) s2 += yv[k][q] * yv[k][q];
           }
           s2 = sqrt(wave_sum(s2));
@@ -365,13 +372,14 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
     if (j == p || done[j] != 0.0) continue;
     T* y = A + (int64_t)j * lda;
     double dot = 0.0;
+    const int rl = i0 + lane < i ? i0 + lane + 64 : i0 + lane;  // first row >= i congruent to lane
     if (tv != 0.0)
-      for (int r = i + lane; r < m; r += 64) dot += x[r - i] * (double)y[r];
+      for (int r = rl; r < m; r += 64) dot += x[r - i] * (double)y[r];
     dot = wave_sum(dot);
     const double f = tv * dot;
     const double yi = (double)y[i] - f;
     if (tv != 0.0)
-      for (int r = i + lane; r < m; r += 64) y[r] = static_cast<T>((double)y[r] - f * x[r - i]);
+      for (int r = rl; r < m; r += 64) y[r] = static_cast<T>((double)y[r] - f * x[r - i]);
     const double v1 = vn1[j];
     if (v1 != 0.0) {
       const double ay = fabs((double)static_cast<T>(yi));
@@ -381,7 +389,7 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
       const double temp2 = temp * ratio * ratio;
       if (temp2 <= tol3z) {
         double s = 0.0;
-        for (int r = i + 1 + lane; r < m; r += 64) s += (double)y[r] * (double)y[r];
+        for (int r = rl + (rl == i ? 64 : 0); r < m; r += 64) s += (double)y[r] * (double)y[r];
         s = sqrt(wave_sum(s));
         if (lane == 0) vn1[j] = s, vn2[j] = s;
       } else if (lane == 0) {
@@ -400,6 +408,430 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
     q.pad_ = 0;
     pwr[d.blk0 + ch] = q;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form: one cooperative launch runs every pivot step of a batch.
+//
+// Each work-group is one wave and owns a chunk of NCW columns of one matrix,
+// held in registers for the whole factorization (lane l holds rows l + 64 q,
+// the grouping of the per-step kernel, so every sum is formed in the same
+// order and the factors are bit-identical); lane k keeps column k's norms.
+// Waves exchange data only through 64-bit words whose low half carries the
+// number of the step the data is for (values are split into 32-bit halves):
+// at the end of a step a wave writes its chunk argmax and that candidate
+// column for the next step, and a step starts once the reader has seen the
+// current tag on every chunk argmax of its matrix; the pivot column is then
+// read from its owner's candidate words the same way.  No flags, fences or
+// barriers are needed: a word is either old (wrong tag) or complete.  Two
+// slots alternate by step parity; a slot is rewritten two steps later, after
+// every wave of the matrix has published the step in between and so has
+// finished reading it.  The buffers are zeroed before the launch (tag 0 is
+// never current).  Matrices never wait on each other, and all waves of a
+// matrix reach the same stop decision at the same step.  Every wait is
+// bounded: past the spin limit a wave raises `err` and exits, and the others
+// exit when they see it.
+// ---------------------------------------------------------------------------
+constexpr long long PQR_SPIN = 1ll << 22;
+constexpr int PQR_POLL = 8;  // chunk argmax words per lane and poll: matrices up to 512 chunks
+
+typedef unsigned long long u64;
+
+__device__ __forceinline__ void st_tag(u64* p, unsigned hi, unsigned tag) {
+  __hip_atomic_store(p, ((u64)hi << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u64 ld_tag(const u64* p) {
+  return __hip_atomic_load(const_cast<u64*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool tag_ok(u64 w, unsigned tag) { return (unsigned)w == tag; }
+__device__ __forceinline__ unsigned hi_of(u64 w) { return (unsigned)(w >> 32); }
+
+template <typename T>
+struct Tagged;
+template <>
+struct Tagged<float> {
+  static constexpr int W = 1;  // 64-bit words per value
+  __device__ static void put(u64* p, float v, unsigned tag) { st_tag(p, __float_as_uint(v), tag); }
+  __device__ static bool get(const u64* p, unsigned tag, float& v) {
+    const u64 a = ld_tag(p);
+    v = __uint_as_float(hi_of(a));
+    return tag_ok(a, tag);
+  }
+};
+template <>
+struct Tagged<double> {
+  static constexpr int W = 2;
+  __device__ static void put(u64* p, double v, unsigned tag) {
+    const u64 b = (u64)__double_as_longlong(v);
+    st_tag(p, (unsigned)(b >> 32), tag);
+    st_tag(p + 1, (unsigned)b, tag);
+  }
+  __device__ static bool get(const u64* p, unsigned tag, double& v) {
+    const u64 a = ld_tag(p), b = ld_tag(p + 1);
+    v = __longlong_as_double((long long)(((u64)hi_of(a) << 32) | hi_of(b)));
+    return tag_ok(a, tag) && tag_ok(b, tag);
+  }
+};
+
+__device__ __forceinline__ bool wave_all(bool ok) { return __ballot(!ok) == 0; }
+
+// Spin bookkeeping of one wait: false once the wait is abandoned.
+__device__ __forceinline__ bool keep_waiting(long long& spins, int* err) {
+  if (++spins > PQR_SPIN) {
+    atomicOr(err, 1);
+    return false;
+  }
+  if ((spins & 31) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+  __builtin_amdgcn_s_sleep(1);
+  return true;
+}
+
+// wave argmax of (val, idx): larger val wins, lowest idx on ties
+__device__ __forceinline__ void wave_argmax(double& bv, int& bi) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(bv, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ov > bv || (ov == bv && oi < bi)) bv = ov, bi = oi;
+  }
+}
+
+template <typename T, int PQ, int NCW>
+__global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, const int2* __restrict__ bmap,
+                                                PQRXch xc, double eps, unsigned long long* stamp) {
+  typedef Tagged<T> TG;
+  const StampScope timing(stamp);
+  const int2 bm = bmap[blockIdx.x];
+  const PQRDesc d = D[bm.x];
+  const int ch = bm.y;
+  const int m = d.m, n = d.n;
+  const int c0 = ch * NCW, c1 = min(n, c0 + NCW);
+  const int gb = d.blk0 + ch;
+  T* A = static_cast<T*>(d.A);
+  const int64_t lda = d.lda;
+  const int lane = threadIdx.x;
+  const double tol3z = sqrt(DBL_EPSILON);
+  const size_t pub_stride = (size_t)xc.rows * TG::W;
+  // a valid rank even if a wait is abandoned (the caller then reports the error)
+  if (ch == 0 && lane == 0) d.rank_out[0] = 0;
+
+  // columns c0 .. c0 + NCW - 1 into registers; lane k keeps column k's norms
+  T y[NCW][PQ];
+  double s[NCW];
+#pragma unroll
+  for (int k = 0; k < NCW; ++k) {
+    const int j = c0 + k;
+    const T* col = A + (int64_t)(j < c1 ? j : 0) * lda;
+    s[k] = 0.0;
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const int r = lane + 64 * q;
+      y[k][q] = (j < c1 && r < m) ? col[r] : T(0);
+      if (r < m) s[k] += (double)y[k][q] * (double)y[k][q];
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int k = 0; k < NCW; ++k) s[k] += __shfl_xor(s[k], o, 64);
+  double myv1 = 0.0;
+#pragma unroll
+  for (int k = 0; k < NCW; ++k)
+    if (lane == k) myv1 = sqrt(s[k]);
+  double myv2 = myv1;
+  bool mydone = !(lane < NCW && c0 + lane < c1);
+  // squared Frobenius norm per 8-column group, summed as the per-step
+  // initialisation does (its 4 waves take columns v and v + 4 of the group)
+#pragma unroll
+  for (int g = 0; g < NCW / 8; ++g) {
+    double w[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = 8 * g + v, b = a + 4;
+      w[v] = c0 + a < c1 ? s[a] : 0.0;
+      if (c0 + b < c1) w[v] += s[b];
+    }
+    if (lane == g && c0 + 8 * g < n) {
+      u64* f = xc.frop + 2 * ((size_t)d.g0 + ch * (NCW / 8) + g);
+      Tagged<double>::put(f, (w[0] + w[1]) + (w[2] + w[3]), 1u);
+    }
+  }
+
+  // publishes the chunk argmax and its candidate column (rows `from` and
+  // below) for the step whose tag is `tag`, into slot `slot`
+  auto publish = [&](int slot, unsigned tag, int from) {
+    double bv = (!mydone) ? myv1 : -1.0;
+    int bi = (!mydone) ? c0 + lane : INT_MAX;
+    wave_argmax(bv, bi);
+    if (bi != INT_MAX) {
+      const int ks = bi - c0;
+      u64* pub = xc.pub + ((size_t)slot * xc.G + gb) * pub_stride;
+#pragma unroll
+      for (int k = 0; k < NCW; ++k)
+        if (k == ks)
+#pragma unroll
+          for (int q = 0; q < PQ; ++q) {
+            const int r = lane + 64 * q;
+            if (r >= from && r < m) TG::put(pub + (size_t)r * TG::W, y[k][q], tag);
+          }
+    }
+    if (lane == 0) {
+      u64* pw = xc.part + 3 * ((size_t)slot * xc.G + gb);
+      const u64 b = (u64)__double_as_longlong(bv);
+      st_tag(pw, (unsigned)(b >> 32), tag);
+      st_tag(pw + 1, (unsigned)b, tag);
+      st_tag(pw + 2, (unsigned)bi, tag);
+    }
+  };
+  publish(0, 1u, 0);
+
+  double r00 = 0.0, floor_v = 0.0;
+  const int kmax = min(m, n);
+  int i = 0;
+  for (;; ++i) {
+    const unsigned tag = (unsigned)i + 1u;
+    const int slot = i & 1;
+    // global argmax over the chunk candidates of this matrix
+    double bv = -1.0;
+    int bi = INT_MAX;
+    {
+      const u64* pr = xc.part + 3 * ((size_t)slot * xc.G + d.blk0);
+      long long spins = 0;
+      for (;;) {
+        bool ok = true;
+        double lv = -1.0;
+        int li = INT_MAX;
+        u64 w0[PQR_POLL], w1[PQR_POLL], w2[PQR_POLL];
+#pragma unroll
+        for (int u = 0; u < PQR_POLL; ++u) {
+          const int k = lane + 64 * u;
+          if (k < d.nblk) {
+            w0[u] = ld_tag(pr + 3 * k);
+            w1[u] = ld_tag(pr + 3 * k + 1);
+            w2[u] = ld_tag(pr + 3 * k + 2);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < PQR_POLL; ++u) {
+          const int k = lane + 64 * u;
+          if (k < d.nblk) {
+            ok = ok && tag_ok(w0[u], tag) && tag_ok(w1[u], tag) && tag_ok(w2[u], tag);
+            const double v = __longlong_as_double((long long)(((u64)hi_of(w0[u]) << 32) | hi_of(w1[u])));
+            const int ix = (int)hi_of(w2[u]);
+            if (v > lv || (v == lv && ix < li)) lv = v, li = ix;
+          }
+        }
+        if (wave_all(ok)) {
+          bv = lv;
+          bi = li;
+          break;
+        }
+        if (!keep_waiting(spins, xc.err)) return;
+      }
+    }
+    wave_argmax(bv, bi);
+    const int p = bi;
+    bool stop = i >= kmax || p < 0 || p >= n || bv < 0.0;
+    // (an empty matrix publishes no Frobenius-norm groups; it stops here)
+    if (i == 0 && !stop) {
+      // the per-step form's reduction: thread t of 256 sums groups t, t + 256, ...
+      const int ng = max(1, (n + 7) / 8);
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int gb0 = 0; gb0 < ng; gb0 += 256) {
+        double f[4];
+        long long spins = 0;
+        for (;;) {
+          bool ok = true;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int g = gb0 + 64 * v + lane;
+            f[v] = 0.0;
+            if (g < ng) ok = Tagged<double>::get(xc.frop + 2 * ((size_t)d.g0 + g), 1u, f[v]) && ok;
+          }
+          if (wave_all(ok)) break;
+          if (!keep_waiting(spins, xc.err)) return;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (gb0 + 64 * v + lane < ng) acc[v] += f[v];
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
+      floor_v = d.noise * sqrt((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    }
+    double beta = 0.0, tv = 0.0, scal = 1.0;
+    double xr[PQ];  // pivot column, then the reflector, at rows lane + 64 q (zero above row i)
+    if (!stop) {
+      const u64* pc = xc.pub + ((size_t)slot * xc.G + d.blk0 + p / NCW) * pub_stride;
+      double xs[PQ];  // rows i + 64 w + lane, the per-step form's grouping of ||x||^2
+      long long spins = 0;
+      for (;;) {
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+          const int r = lane + 64 * q;
+          T v = T(0);
+          if (r >= i && r < m) ok = TG::get(pc + (size_t)r * TG::W, tag, v) && ok;
+          xr[q] = (double)v;
+          const int rs = i + 64 * q + lane;
+          T u = T(0);
+          if (rs < m) ok = TG::get(pc + (size_t)rs * TG::W, tag, u) && ok;
+          xs[q] = (double)u;
+        }
+        if (wave_all(ok)) break;
+        if (!keep_waiting(spins, xc.err)) return;
+      }
+      double part[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < PQ && q < 4; ++q) {
+        const int rs = i + 64 * q + lane;
+        if (rs > i && rs < m) part[q] = xs[q] * xs[q];
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) part[w] += __shfl_xor(part[w], o, 64);
+      const double xn2 = (part[0] + part[1]) + (part[2] + part[3]);
+      const double alpha = __shfl(xs[0], 0, 64);
+      house_scalars(alpha, xn2, beta, tv, scal);
+      if (i == 0) r00 = fabs(beta);
+      stop = fabs(beta) <= floor_v;
+      if (d.forced >= 0)
+        stop = stop || i >= d.forced;
+      else if (i > 0)
+        stop = stop || fabs(beta) < eps * r00;
+    }
+    if (stop) break;
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const int r = lane + 64 * q;
+      if (r == i)
+        xr[q] = 1.0;
+      else if (r > i && tv != 0.0)
+        xr[q] *= scal;
+    }
+    if (ch == 0) {
+      if (d.V) {
+        T* vc = static_cast<T*>(d.V) + (int64_t)i * m;
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+          const int r = lane + 64 * q;
+          if (r < m) vc[r] = r < i ? T(0) : static_cast<T>(xr[q]);
+        }
+      }
+      if (lane == 0) {
+        if (d.tau) static_cast<T*>(d.tau)[i] = static_cast<T>(tv);
+        if (d.piv_out) d.piv_out[i] = p;
+      }
+    }
+    // the pivot column goes out final (R entries above, beta, zeros below)
+    if (p >= c0 && p < c1) {
+#pragma unroll
+      for (int k = 0; k < NCW; ++k)
+        if (c0 + k == p) {
+          T* col = A + (int64_t)p * lda;
+#pragma unroll
+          for (int q = 0; q < PQ; ++q) {
+            const int r = lane + 64 * q;
+            if (r < m) col[r] = r < i ? y[k][q] : (r == i ? static_cast<T>(beta) : T(0));
+          }
+        }
+      if (lane == p - c0) mydone = true;
+    }
+    // H_i on the live columns, all NCW side by side
+    const bool mylive = !mydone;
+    const unsigned long long livem = __ballot(mylive);
+    double dot[NCW];
+    T yold[NCW];
+#pragma unroll
+    for (int k = 0; k < NCW; ++k) {
+      dot[k] = 0.0;
+      yold[k] = T(0);
+#pragma unroll
+      for (int q = 0; q < PQ; ++q) {
+        const int r = lane + 64 * q;
+        if (tv != 0.0 && r >= i && r < m) dot[k] += xr[q] * (double)y[k][q];
+        if (q == (i >> 6)) yold[k] = y[k][q];
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int k = 0; k < NCW; ++k) dot[k] += __shfl_xor(dot[k], o, 64);
+    double mydot = 0.0;
+    T myyold = T(0);
+#pragma unroll
+    for (int k = 0; k < NCW; ++k) {
+      const T yk = __shfl(yold[k], i & 63, 64);
+      if (lane == k) mydot = dot[k], myyold = yk;
+    }
+    if (tv != 0.0)
+#pragma unroll
+      for (int k = 0; k < NCW; ++k) {
+        if (!((livem >> k) & 1)) continue;
+        const double f = tv * dot[k];
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+          const int r = lane + 64 * q;
+          if (r >= i && r < m) y[k][q] = static_cast<T>((double)y[k][q] - f * xr[q]);
+        }
+      }
+    // norm downdate (LAPACK Working Note 176), lane k for column k
+    bool myneed = false;
+    double v1n = myv1;
+    if (mylive && myv1 != 0.0) {
+      const double f = tv * mydot;
+      const double yi = (double)myyold - f;
+      const double ay = fabs((double)static_cast<T>(yi));
+      double temp = 1.0 - (ay / myv1) * (ay / myv1);
+      temp = temp > 0.0 ? temp : 0.0;
+      const double ratio = myv1 / myv2;
+      const double temp2 = temp * ratio * ratio;
+      myneed = temp2 <= tol3z;
+      v1n = myv1 * sqrt(temp);
+    }
+    const unsigned long long needm = __ballot(myneed);
+    if (needm) {
+#pragma unroll
+      for (int k = 0; k < NCW; ++k) {
+        dot[k] = 0.0;
+        if ((needm >> k) & 1)
+#pragma unroll
+          for (int q = 0; q < PQ; ++q) {
+            const int r = lane + 64 * q;
+            if (r > i && r < m) dot[k] += (double)y[k][q] * (double)y[k][q];
+          }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < NCW; ++k)
+          if ((needm >> k) & 1) dot[k] += __shfl_xor(dot[k], o, 64);
+#pragma unroll
+      for (int k = 0; k < NCW; ++k)
+        if (lane == k && myneed) v1n = sqrt(dot[k]);
+    }
+    if (mylive) {
+      myv1 = v1n;
+      if (myneed) myv2 = v1n;
+    }
+    publish(slot ^ 1, tag + 1u, i + 1);
+  }
+  // stopped at step i: the columns still held go back to A, and the rank out
+  const unsigned long long keep = __ballot(!mydone);
+#pragma unroll
+  for (int k = 0; k < NCW; ++k) {
+    if (!((keep >> k) & 1)) continue;
+    T* col = A + (int64_t)(c0 + k) * lda;
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const int r = lane + 64 * q;
+      if (r < m) col[r] = y[k][q];
+    }
+  }
+  if (ch == 0 && lane == 0) d.rank_out[0] = i;
 }
 
 template <typename T>
@@ -432,15 +864,19 @@ void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRSta
   if (nblocks <= 0) return;
   const size_t lds = (size_t)std::max(1, max_m) * sizeof(double);
   if (lds > 64 * 1024) throw Error(SPAQR_EARG, "rank-revealing QR block taller than 8192 rows");
-  const int rows = max_m - i;
+  const int rows = max_m - (i & ~63);
 #define SPAQR_PQR_GO(Q, C)                                                                                   \
   hipLaunchKernelGGL((k_pqr_step<T, Q, C>), dim3(nblocks), dim3(BS), lds, s, d_desc, states, parts, total_parts, \
                      bmap, active, i, eps, stamp)
   if (cw == PQR_CW) {
     if (rows <= 128)
       SPAQR_PQR_GO(2, PQR_CW / 4);
+    else if (rows <= 192)
+      SPAQR_PQR_GO(3, PQR_CW / 4);
     else if (rows <= 256)
       SPAQR_PQR_GO(4, PQR_CW / 4);
+    else if (rows <= 320)
+      SPAQR_PQR_GO(5, PQR_CW / 4);
     else
       SPAQR_PQR_GO(0, PQR_CW / 4);
   } else {
@@ -448,6 +884,91 @@ void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRSta
   }
 #undef SPAQR_PQR_GO
   SPAQR_HIP(hipGetLastError());
+}
+
+namespace {
+
+// waves of k_pqr_run<T, PQ, NCW> that fit on the device at once (0 without
+// cooperative launch support); queried once per kernel
+template <typename T, int PQ, int NCW>
+int run_capacity() {
+  static int cap = -1;
+  if (cap < 0) {
+    int dev = 0, cus = 0, per = 0, coop = 0;
+    SPAQR_HIP(hipGetDevice(&dev));
+    SPAQR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    SPAQR_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    SPAQR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pqr_run<T, PQ, NCW>, 64, 0));
+    cap = coop ? per * cus : 0;
+  }
+  return cap;
+}
+
+template <typename T, int PQ>
+int run_capacity_w(int ncw) {
+  if (ncw == 8) return run_capacity<T, PQ, 8>();
+  if (ncw == 16) return run_capacity<T, PQ, 16>();
+  if constexpr (PQ == 2) return run_capacity<T, PQ, 32>();
+  return 0;
+}
+
+}  // namespace
+
+// Chunk width of the persistent form (columns per wave): the narrowest of 8,
+// 16, 32 (16 at most above 128 rows) that keeps every matrix at or below 256
+// chunks (at most 512 with the widest), within the co-resident limit; 0 when
+// the form does not apply.
+template <typename T>
+int pqr_run_width(int max_m, const std::vector<int>& ns, int* rows) {
+  // Opt-in (SPAQR_PQR_PERSISTENT set): the form has not yet run on every
+  // workload shape.  SPAQR_NO_COOP (no cooperative launches, for tools that
+  // cannot follow them) and SPAQR_PQR_STEPS (one launch per step) keep the
+  // other form.
+  if (!std::getenv("SPAQR_PQR_PERSISTENT")) return 0;
+  if (std::getenv("SPAQR_NO_COOP") || std::getenv("SPAQR_PQR_STEPS")) return 0;
+  if (max_m > PQR_RUN_ROWS || ns.empty()) return 0;
+  const int pq = max_m <= 128 ? 2 : 4;
+  *rows = 64 * pq;
+  const int top = pq == 2 ? 32 : 16;  // 32 columns of 256 rows do not fit in registers
+  for (int ncw = 8; ncw <= top; ncw *= 2) {
+    int64_t total = 0;
+    int widest = 0;
+    for (int n : ns) {
+      const int nb = std::max(1, (n + ncw - 1) / ncw);
+      total += nb;
+      widest = std::max(widest, nb);
+    }
+    const int cap = pq == 2 ? run_capacity_w<T, 2>(ncw) : run_capacity_w<T, 4>(ncw);
+    if (total <= cap && (widest <= 256 || (ncw == top && widest <= PQR_POLL * 64))) return ncw;
+  }
+  return 0;
+}
+
+template <typename T>
+void launch_pqr_run(const PQRDesc* d_desc, int nblocks, const int2* bmap, const PQRXch& xc, double eps, int cw,
+                    unsigned long long* stamp, hipStream_t s) {
+  if (nblocks <= 0) return;
+  if (nblocks != xc.G) throw Error(SPAQR_EARG, "internal: persistent pivoted QR grid mismatch");
+  const int pq = xc.rows / 64;
+  const void* fn = nullptr;
+#define SPAQR_PQR_RUN(Q, C) \
+  if (pq == Q && cw == C) fn = reinterpret_cast<const void*>(&k_pqr_run<T, Q, C>);
+  SPAQR_PQR_RUN(2, 8)
+  SPAQR_PQR_RUN(2, 16)
+  SPAQR_PQR_RUN(2, 32)
+  SPAQR_PQR_RUN(4, 8)
+  SPAQR_PQR_RUN(4, 16)
+#undef SPAQR_PQR_RUN
+  if (!fn || xc.rows != 64 * pq) throw Error(SPAQR_EARG, "internal: unsupported persistent pivoted QR shape");
+  const int cap = pq == 2 ? run_capacity_w<T, 2>(cw) : run_capacity_w<T, 4>(cw);
+  if (nblocks > cap) throw Error(SPAQR_EARG, "internal: persistent pivoted QR exceeds the co-resident limit");
+  PQRXch x = xc;
+  const PQRDesc* dd = d_desc;
+  const int2* bm = bmap;
+  double e = eps;
+  unsigned long long* st = stamp;
+  void* args[] = {(void*)&dd, (void*)&bm, (void*)&x, (void*)&e, (void*)&st};
+  SPAQR_HIP(hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(64), args, 0, s));
 }
 
 template <typename T>
@@ -461,7 +982,10 @@ void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int st
   template void launch_pqr_init<T>(const PQRDesc*, int, PQRState*, PQRPart*, const int2*, hipStream_t); \
   template void launch_pqr_step<T>(const PQRDesc*, int, int, PQRState*, PQRPart*, const int2*, int*, int, \
                                    double, int, int, unsigned long long*, hipStream_t);               \
-  template void launch_pqr_finish<T>(const PQRDesc*, int, PQRState*, int, hipStream_t);
+  template void launch_pqr_finish<T>(const PQRDesc*, int, PQRState*, int, hipStream_t);                   \
+  template int pqr_run_width<T>(int, const std::vector<int>&, int*);                                     \
+  template void launch_pqr_run<T>(const PQRDesc*, int, const int2*, const PQRXch&, double, int,            \
+                                  unsigned long long*, hipStream_t);
 
 SPAQR_PQR_INST(double)
 SPAQR_PQR_INST(float)

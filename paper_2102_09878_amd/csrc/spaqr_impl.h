@@ -185,7 +185,8 @@ struct PQRDesc {
   double noise;
   int m, n, forced;
   int blk0, nblk;    // this matrix's column chunks in the launch (set by the launcher)
-  int cw;            // columns per chunk (PQR_CW; set by the launcher)
+  int cw;            // columns per chunk (set by the launcher)
+  int g0;            // first 8-column group of this matrix (persistent form)
 };
 
 // Per-matrix state of the step-synchronous pivoted QR, double-buffered by
@@ -327,6 +328,34 @@ void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRSta
                      unsigned long long* stamp, hipStream_t s);
 template <typename T>
 void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int steps, hipStream_t s);
+// Persistent form: all pivot steps of a batch in one cooperative launch of
+// one-wave work-groups (chunks of the matrices' columns) that exchange, per
+// step, their chunk argmax and candidate pivot column through the buffers
+// below, as 64-bit words tagged with the step number.  Only for batches whose
+// tallest matrix has at most PQR_RUN_ROWS rows; the factors are bit-identical
+// to the one-launch-per-step form.  The buffers must be zeroed before the
+// launch.
+constexpr int PQR_RUN_ROWS = 256;
+struct PQRXch {
+  unsigned long long* part;  // [2][G][3] chunk argmax (value halves, column), by step parity
+  unsigned long long* pub;   // [2][G][rows][sizeof(T) / 4] candidate columns
+  unsigned long long* frop;  // [groups][2] squared Frobenius norm per 8-column group
+  int* err;                  // set (and every wave exits) when a wait exceeds its spin limit
+  int G;                     // work-groups (chunks) in the launch
+  int rows;                  // rows per candidate column (64 PQ)
+};
+// 64-bit words of the exchange buffers of a launch
+inline size_t pqr_xch_words(int G, int rows, int groups, size_t tsize) {
+  return 6 * (size_t)G + 2 * (size_t)G * rows * (tsize / 4) + 2 * (size_t)groups;
+}
+// Chooses the chunk width for a batch (columns per work-group), or returns 0
+// when the persistent form does not apply (too tall, or more work-groups than
+// can be co-resident).  ns: column counts of the matrices.
+template <typename T>
+int pqr_run_width(int max_m, const std::vector<int>& ns, int* rows);
+template <typename T>
+void launch_pqr_run(const PQRDesc* d_desc, int nblocks, const int2* bmap, const PQRXch& xc, double eps, int cw,
+                    unsigned long long* stamp, hipStream_t s);
 template <typename T>
 void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, int max_c, hipStream_t s);
 template <typename T>
