@@ -509,6 +509,7 @@ class Factorizer {
     const int2* dmap = upload(bmap);
     auto* states = static_cast<PQRState*>(H.arena.alloc(2 * q.size() * sizeof(PQRState)));
     auto* parts = static_cast<PQRPart*>(H.arena.alloc(2 * (size_t)total * sizeof(PQRPart)));
+    auto* frop = static_cast<double*>(H.arena.alloc((size_t)total * sizeof(double)));
     int* active = upload(std::vector<int>{live_m});
     int* h_active = static_cast<int*>(H.stage.alloc(sizeof(int)));
     static const bool dbg = std::getenv("SPAQR_DEBUG_PQR") != nullptr;
@@ -518,7 +519,7 @@ class Factorizer {
       SPAQR_HIP(hipEventCreate(&e1));
       SPAQR_HIP(hipEventRecord(e0, st));
     }
-    launch_pqr_init<T>(d, total, states, parts, dmap, st);
+    launch_pqr_init<T>(d, total, states, parts, frop, dmap, st);
     ++launches_;
     int steps = 0;
     timed_steps_.clear();
@@ -526,7 +527,7 @@ class Factorizer {
       const bool timed = H.kt.pick("pqr_step");
       unsigned long long* stamp = timed ? H.kt.stamp(st) : nullptr;
       if (timed) timed_steps_.push_back(steps);
-      launch_pqr_step<T>(d, total, total, states, parts, dmap, active, steps, eps_, max_m, cw, stamp, st);
+      launch_pqr_step<T>(d, total, total, states, parts, frop, dmap, active, steps, eps_, max_m, cw, stamp, st);
       ++launches_;
       ++steps;
       if (steps % 16 == 0 && steps < kmax) {

@@ -92,7 +92,7 @@ __device__ __forceinline__ void chunk_argmax(const double* vn1, const double* do
 template <typename T>
 __global__ __launch_bounds__(BS) void k_pqr_init(const PQRDesc* __restrict__ D,
                                                  PQRState* __restrict__ S, PQRPart* __restrict__ parts,
-                                                 const int2* __restrict__ bmap) {
+                                                 double* __restrict__ frop, const int2* __restrict__ bmap) {
   const int2 bm = bmap[blockIdx.x];
   const PQRDesc d = D[bm.x];
   const T* A = static_cast<const T*>(d.A);
@@ -124,10 +124,10 @@ __global__ __launch_bounds__(BS) void k_pqr_init(const PQRDesc* __restrict__ D,
   if (tid == 0) {
     PQRPart p;
     p.val = bv;
-    p.fro = fro;
     p.idx = bi;
     p.pad_ = 0;
     parts[d.blk0 + bm.y] = p;
+    frop[d.blk0 + bm.y] = fro;
     if (bm.y == 0) {
       PQRState s;
       s.r00 = 0.0;
@@ -166,6 +166,7 @@ struct StampScope {
 template <typename T, int PQ, int NC>
 __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, PQRState* __restrict__ S,
                                                  PQRPart* __restrict__ parts, int total_parts,
+                                                 const double* __restrict__ frop,
                                                  const int2* __restrict__ bmap, int* __restrict__ active,
                                                  int i, double eps, unsigned long long* stamp) {
   const StampScope timing(stamp);
@@ -195,17 +196,20 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
   double* done = d.work + 2 * n;
   double pval[PL];
   int pidx[PL];
-  double pfro[PL];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
     const int k = tid + u * BS;
     if (k < d.nblk) {
       const PQRPart q = prd[d.blk0 + k];
-      pval[u] = q.val, pidx[u] = q.idx, pfro[u] = q.fro;
+      pval[u] = q.val, pidx[u] = q.idx;
     } else {
-      pval[u] = -1.0, pidx[u] = INT_MAX, pfro[u] = 0.0;
+      pval[u] = -1.0, pidx[u] = INT_MAX;
     }
   }
+  // squared Frobenius norm (first step only): thread t sums chunks t, t + BS, ...
+  double fro = 0.0;
+  if (i == 0)
+    for (int k = tid; k < d.nblk; k += BS) fro += frop[d.blk0 + k];
   // Register rows form a 64-aligned window: lane l holds rows i0 + l + 64 q,
   // so every per-lane partial sum runs over the rows congruent to l mod 64
   // in ascending order, whatever the step (the persistent form below keeps
@@ -246,17 +250,14 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
     return;
   }
   // global pivot and (first step) the Frobenius norm
-  double bv = -1.0, fro = 0.0;
+  double bv = -1.0;
   int bi = INT_MAX;
 #pragma unroll
-  for (int u = 0; u < PL; ++u) {
+  for (int u = 0; u < PL; ++u)
     if (pval[u] > bv || (pval[u] == bv && pidx[u] < bi)) bv = pval[u], bi = pidx[u];
-    fro += pfro[u];
-  }
   for (int k = tid + PL * BS; k < d.nblk; k += BS) {
     const PQRPart q = prd[d.blk0 + k];
     if (q.val > bv || (q.val == bv && q.idx < bi)) bv = q.val, bi = q.idx;
-    fro += q.fro;
   }
   block_argmax(bv, bi, shv, shi);
   double floor_v = sp.floor;
@@ -403,7 +404,6 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
   if (tid == 0) {
     PQRPart q;
     q.val = bv;
-    q.fro = 0.0;
     q.idx = bi;
     q.pad_ = 0;
     pwr[d.blk0 + ch] = q;
@@ -850,24 +850,24 @@ __global__ __launch_bounds__(BS) void k_pqr_finish(const PQRDesc* __restrict__ D
 }  // namespace
 
 template <typename T>
-void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPart* parts,
+void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPart* parts, double* frop,
                      const int2* bmap, hipStream_t s) {
   if (nblocks <= 0) return;
-  hipLaunchKernelGGL(k_pqr_init<T>, dim3(nblocks), dim3(BS), 0, s, d_desc, states, parts, bmap);
+  hipLaunchKernelGGL(k_pqr_init<T>, dim3(nblocks), dim3(BS), 0, s, d_desc, states, parts, frop, bmap);
   SPAQR_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRState* states,
-                     PQRPart* parts, const int2* bmap, int* active, int i, double eps, int max_m, int cw,
-                     unsigned long long* stamp, hipStream_t s) {
+                     PQRPart* parts, const double* frop, const int2* bmap, int* active, int i, double eps,
+                     int max_m, int cw, unsigned long long* stamp, hipStream_t s) {
   if (nblocks <= 0) return;
   const size_t lds = (size_t)std::max(1, max_m) * sizeof(double);
   if (lds > 64 * 1024) throw Error(SPAQR_EARG, "rank-revealing QR block taller than 8192 rows");
   const int rows = max_m - (i & ~63);
 #define SPAQR_PQR_GO(Q, C)                                                                                   \
   hipLaunchKernelGGL((k_pqr_step<T, Q, C>), dim3(nblocks), dim3(BS), lds, s, d_desc, states, parts, total_parts, \
-                     bmap, active, i, eps, stamp)
+                     frop, bmap, active, i, eps, stamp)
   if (cw == PQR_CW) {
     if (rows <= 128)
       SPAQR_PQR_GO(2, PQR_CW / 4);
@@ -979,9 +979,9 @@ void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int st
 }
 
 #define SPAQR_PQR_INST(T)                                                                             \
-  template void launch_pqr_init<T>(const PQRDesc*, int, PQRState*, PQRPart*, const int2*, hipStream_t); \
-  template void launch_pqr_step<T>(const PQRDesc*, int, int, PQRState*, PQRPart*, const int2*, int*, int, \
-                                   double, int, int, unsigned long long*, hipStream_t);               \
+  template void launch_pqr_init<T>(const PQRDesc*, int, PQRState*, PQRPart*, double*, const int2*, hipStream_t); \
+  template void launch_pqr_step<T>(const PQRDesc*, int, int, PQRState*, PQRPart*, const double*, const int2*,  \
+                                   int*, int, double, int, int, unsigned long long*, hipStream_t);              \
   template void launch_pqr_finish<T>(const PQRDesc*, int, PQRState*, int, hipStream_t);                   \
   template int pqr_run_width<T>(int, const std::vector<int>&, int*);                                     \
   template void launch_pqr_run<T>(const PQRDesc*, int, const int2*, const PQRXch&, double, int,            \

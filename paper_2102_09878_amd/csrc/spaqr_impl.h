@@ -195,8 +195,9 @@ struct PQRState {
   double r00, floor, beta;
   int pivot, pstep, rank, stopped;
 };
-struct PQRPart {
-  double val, fro;
+// chunk argmax of one step (one 16-byte load per chunk when scanned)
+struct alignas(16) PQRPart {
+  double val;
   int idx, pad_;
 };
 
@@ -312,19 +313,20 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h_desc, const QR
                int* launches);
 // Column-pivoted QR of a batch, one launch per pivot step (columns split in
 // chunks of PQR_CW over work-groups).  The caller provides device scratch:
-// states (2 per matrix), parts (2 per chunk), bmap (one int2 per chunk) and
-// an `active` counter; h_desc must already carry blk0/nblk.
+// states (2 per matrix), parts (2 per chunk), frop (squared Frobenius norm
+// per chunk, one per chunk), bmap (one int2 per chunk) and an `active`
+// counter; h_desc must already carry blk0/nblk.
 constexpr int PQR_CW = 8;
 // self-timing stamps of one timed launch: STAMP_SLOTS slots of STAMP_STRIDE
 // words (complement of the earliest start, latest end, padding)
 constexpr int STAMP_SLOTS = 32;
 constexpr int STAMP_STRIDE = 8;
 template <typename T>
-void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPart* parts,
+void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPart* parts, double* frop,
                      const int2* bmap, hipStream_t s);
 template <typename T>
 void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRState* states,
-                     PQRPart* parts, const int2* bmap, int* active, int i, double eps, int max_m, int cw,
+                     PQRPart* parts, const double* frop, const int2* bmap, int* active, int i, double eps, int max_m, int cw,
                      unsigned long long* stamp, hipStream_t s);
 template <typename T>
 void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int steps, hipStream_t s);
