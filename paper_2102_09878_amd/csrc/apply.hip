@@ -21,6 +21,7 @@ namespace spaqr {
 namespace {
 
 constexpr int BS = 256;
+constexpr int UPW = 32;  // row-update loads in flight per thread
 constexpr int APPLY_MAX = 4096;  // largest cluster handled by one block (32 KB LDS vector)
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -38,52 +39,83 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // Solve R t = t (upper, column-major, ld) in place in LDS, blocks of 64:
-// wave 0 solves each diagonal block without barriers, all threads update
-// the rows above it.
+// the block's diagonal 64 x 64 tile is staged in LDS by all threads (one
+// round trip), wave 0 solves it without barriers or memory waits, then all
+// threads update the rows above it.
 template <typename T>
-__device__ void trsv_upper(const T* __restrict__ R, int64_t ld, int n, double* t) {
+__device__ void trsv_upper(const T* __restrict__ R, int64_t ld, int n, double* t, T (*Ds)[65]) {
   const int tid = threadIdx.x, lane = tid & 63;
   for (int jb = ((n - 1) / 64) * 64; jb >= 0; jb -= 64) {
-    const int je = min(n, jb + 64);
-    if (tid < 64) {
-      double v = jb + lane < je ? t[jb + lane] : 0.0;
-      for (int j = je - 1; j >= jb; --j) {
-        if (lane == j - jb) v = v / (double)R[j + j * ld];
-        const double tj = __shfl(v, j - jb, 64);
-        if (lane < j - jb) v -= tj * (double)R[jb + lane + j * ld];
-      }
-      if (jb + lane < je) t[jb + lane] = v;
+    const int nb = min(n, jb + 64) - jb;
+    for (int e = tid; e < 64 * 64; e += BS) {
+      const int r = e & 63, c = e >> 6;
+      if (r < nb && c < nb) Ds[c][r] = R[jb + r + (int64_t)(jb + c) * ld];
     }
     __syncthreads();
+    if (tid < 64) {
+      double v = lane < nb ? t[jb + lane] : 0.0;
+      for (int c = nb - 1; c >= 0; --c) {
+        if (lane == c) v = v / (double)Ds[c][c];
+        const double tj = __shfl(v, c, 64);
+        if (lane < c) v -= tj * (double)Ds[c][lane];
+      }
+      if (lane < nb) t[jb + lane] = v;
+    }
+    __syncthreads();
+    // rows above the block: loads issued 32 at a time ahead of the (ordered) sums
+    const int ldi = (int)ld;
     for (int i = tid; i < jb; i += BS) {
+      const T* rp = R + (int64_t)jb * ld + i;
       double acc = 0.0;
-      for (int j = jb; j < je; ++j) acc += (double)R[i + j * ld] * t[j];
+#pragma unroll 1
+      for (int h = 0; h < 64; h += UPW) {
+        T rv[UPW];
+#pragma unroll
+        for (int c = 0; c < UPW; ++c) rv[c] = rp[min(h + c, nb - 1) * ldi];
+#pragma unroll
+        for (int c = 0; c < UPW; ++c)
+          if (h + c < nb) acc += (double)rv[c] * t[jb + h + c];
+      }
       t[i] -= acc;
     }
     __syncthreads();
   }
 }
 
-// Solve R^T y = t (R upper) in place, forward over blocks of 64.
+// Solve R^T y = t (R upper) in place, forward over blocks of 64 (diagonal
+// tile staged in LDS as above).
 template <typename T>
-__device__ void trsv_upper_t(const T* __restrict__ R, int64_t ld, int n, double* t) {
+__device__ void trsv_upper_t(const T* __restrict__ R, int64_t ld, int n, double* t, T (*Ds)[65]) {
   const int tid = threadIdx.x, lane = tid & 63;
   for (int jb = 0; jb < n; jb += 64) {
-    const int je = min(n, jb + 64);
+    const int je = min(n, jb + 64), nb = je - jb;
+    for (int e = tid; e < 64 * 64; e += BS) {
+      const int r = e & 63, c = e >> 6;
+      if (r < nb && c < nb) Ds[c][r] = R[jb + r + (int64_t)(jb + c) * ld];
+    }
+    __syncthreads();
     if (tid < 64) {
-      double v = jb + lane < je ? t[jb + lane] : 0.0;
-      for (int j = jb; j < je; ++j) {
-        if (lane == j - jb) v = v / (double)R[j + j * ld];
-        const double yj = __shfl(v, j - jb, 64);
-        if (lane > j - jb && jb + lane < je) v -= (double)R[j + (jb + lane) * ld] * yj;
+      double v = lane < nb ? t[jb + lane] : 0.0;
+      for (int c = 0; c < nb; ++c) {
+        if (lane == c) v = v / (double)Ds[c][c];
+        const double yj = __shfl(v, c, 64);
+        if (lane > c && lane < nb) v -= (double)Ds[lane][c] * yj;
       }
-      if (jb + lane < je) t[jb + lane] = v;
+      if (lane < nb) t[jb + lane] = v;
     }
     __syncthreads();
     for (int k = je + tid; k < n; k += BS) {
-      const T* col = R + k * ld;
+      const T* col = R + (int64_t)k * ld + jb;
       double acc = 0.0;
-      for (int j = jb; j < je; ++j) acc += (double)col[j] * t[j];
+#pragma unroll 1
+      for (int h = 0; h < 64; h += UPW) {
+        T rv[UPW];
+#pragma unroll
+        for (int c = 0; c < UPW; ++c) rv[c] = col[min(h + c, nb - 1)];
+#pragma unroll
+        for (int c = 0; c < UPW; ++c)
+          if (h + c < nb) acc += (double)rv[c] * t[jb + h + c];
+      }
       t[k] -= acc;
     }
     __syncthreads();
@@ -96,6 +128,7 @@ __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, i
   const ApplyOp op = ops[blockIdx.x];
   __shared__ double t[APPLY_MAX];
   __shared__ double sh[4];
+  __shared__ T Ds[64][65];  // diagonal tile of the triangular solves
   const int tid = threadIdx.x;
   const int n1 = op.n1;
   const T* R = static_cast<const T*>(op.R);
@@ -113,10 +146,10 @@ __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, i
           t[i] -= a;
         }
       __syncthreads();
-      trsv_upper(R, op.ld, n1, t);
+      trsv_upper(R, op.ld, n1, t, Ds);
       for (int i = tid; i < n1; i += BS) x[op.s1[i]] = t[i];
     } else {
-      trsv_upper_t(R, op.ld, n1, t);
+      trsv_upper_t(R, op.ld, n1, t, Ds);
       for (int i = tid; i < n1; i += BS) {
         x[op.s1[i]] = t[i];
         if (op.n2 > 0) work[op.poff + i] = t[i];
@@ -124,9 +157,9 @@ __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, i
     }
   } else if (op.kind == 1) {  // scale
     if (!transpose)
-      trsv_upper(R, op.ld, n1, t);
+      trsv_upper(R, op.ld, n1, t, Ds);
     else
-      trsv_upper_t(R, op.ld, n1, t);
+      trsv_upper_t(R, op.ld, n1, t, Ds);
     for (int i = tid; i < n1; i += BS) x[op.s1[i]] = t[i];
   } else {  // sparsify: Q = H_0 .. H_{r-1}
     const int r = op.n2;
