@@ -25,6 +25,7 @@
 #include <cstdlib>
 
 #include "spaqr_impl.h"
+#include "wave.h"
 
 namespace spaqr {
 
@@ -34,11 +35,7 @@ constexpr int BS = 256;
 constexpr int PL = 6;  // chunk partials per thread fetched up front
 static_assert(PQR_CW == 8, "a pivot step gives each of its 4 waves cw/4 columns");
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   v = wave_sum(v);
@@ -531,9 +528,7 @@ __global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, c
     }
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-    for (int k = 0; k < NCW; ++k) s[k] += __shfl_xor(s[k], o, 64);
+  for (int k = 0; k < NCW; ++k) s[k] = wave_sum(s[k]);
   double myv1 = 0.0;
 #pragma unroll
   for (int k = 0; k < NCW; ++k)
@@ -656,9 +651,7 @@ __global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, c
           if (gb0 + 64 * v + lane < ng) acc[v] += f[v];
       }
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
+      for (int v = 0; v < 4; ++v) acc[v] = wave_sum(acc[v]);
       floor_v = d.noise * sqrt((acc[0] + acc[1]) + (acc[2] + acc[3]));
     }
     double beta = 0.0, tv = 0.0, scal = 1.0;
@@ -690,9 +683,7 @@ __global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, c
         if (rs > i && rs < m) part[q] = xs[q] * xs[q];
       }
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-        for (int w = 0; w < 4; ++w) part[w] += __shfl_xor(part[w], o, 64);
+      for (int w = 0; w < 4; ++w) part[w] = wave_sum(part[w]);
       const double xn2 = (part[0] + part[1]) + (part[2] + part[3]);
       const double alpha = __shfl(xs[0], 0, 64);
       house_scalars(alpha, xn2, beta, tv, scal);
@@ -757,9 +748,7 @@ __global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, c
       }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-      for (int k = 0; k < NCW; ++k) dot[k] += __shfl_xor(dot[k], o, 64);
+    for (int k = 0; k < NCW; ++k) dot[k] = wave_sum(dot[k]);
     double mydot = 0.0;
     T myyold = T(0);
 #pragma unroll
@@ -805,10 +794,8 @@ __global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, c
           }
       }
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-        for (int k = 0; k < NCW; ++k)
-          if ((needm >> k) & 1) dot[k] += __shfl_xor(dot[k], o, 64);
+      for (int k = 0; k < NCW; ++k)
+        if ((needm >> k) & 1) dot[k] = wave_sum(dot[k]);
 #pragma unroll
       for (int k = 0; k < NCW; ++k)
         if (lane == k && myneed) v1n = sqrt(dot[k]);
