@@ -15,6 +15,7 @@
 #include <cfloat>
 
 #include "spaqr_impl.h"
+#include "wave.h"
 
 namespace spaqr {
 
@@ -24,16 +25,12 @@ constexpr int BS = 256;
 constexpr int UPW = 32;  // row-update loads in flight per thread
 constexpr int APPLY_MAX = 4096;  // largest cluster handled by one block (32 KB LDS vector)
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-  v = wave_sum(v);
+  v = wave_sum63(v);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
@@ -252,11 +249,11 @@ __global__ __launch_bounds__(BS) void k_apply_gemv(const ApplyOp* __restrict__ o
         if (nc > 2) a2 += (double)col[i + 2 * op.ld] * ti;
         if (nc > 3) a3 += (double)col[i + 3 * op.ld] * ti;
       }
-      a0 = wave_sum(a0);
-      a1 = wave_sum(a1);
-      a2 = wave_sum(a2);
-      a3 = wave_sum(a3);
-      if (lane == 0) {
+      a0 = wave_sum63(a0);
+      a1 = wave_sum63(a1);
+      a2 = wave_sum63(a2);
+      a3 = wave_sum63(a3);
+      if (lane == 63) {
         double* out = stage + op.nstage + cb;
         out[0] = a0;
         if (nc > 1) out[1] = a1;

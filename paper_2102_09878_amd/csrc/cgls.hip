@@ -8,6 +8,7 @@
 #include <algorithm>
 
 #include "cgls.h"
+#include "wave.h"
 
 namespace spaqr {
 
@@ -15,11 +16,7 @@ namespace {
 
 constexpr int BS = 256;
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 
 __device__ __forceinline__ bool frozen(const int* act, int g) { return act && !act[g]; }
 

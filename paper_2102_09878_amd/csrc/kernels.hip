@@ -17,6 +17,7 @@
 #include <cmath>
 
 #include "spaqr_impl.h"
+#include "wave.h"
 
 namespace spaqr {
 
@@ -35,11 +36,7 @@ struct Unit<float> {
   static constexpr double u = FLT_EPSILON / 2;
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 
 // Sum over the 256 threads of a block; every thread gets the result.
 __device__ __forceinline__ double block_sum(double v, double* sh) {

@@ -38,9 +38,9 @@ static_assert(PQR_CW == 8, "a pivot step gives each of its 4 waves cw/4 columns"
 __device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-  v = wave_sum(v);
+  v = wave_sum63(v);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }

@@ -23,6 +23,7 @@
 #include <cstdlib>
 
 #include "spaqr_impl.h"
+#include "wave.h"
 
 namespace spaqr {
 
@@ -33,16 +34,12 @@ constexpr int NB = QR_NB;
 constexpr int TN = QR_TN;
 constexpr int RS = QR_RS;
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-  v = wave_sum(v);
+  v = wave_sum63(v);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
@@ -185,8 +182,8 @@ __global__ __launch_bounds__(BS) void k_qr_panel(const QRDesc* __restrict__ D, i
 #pragma unroll
     for (int q = 0; q < NB - 1; ++q) {
       if (q < kb - 1) {
-        const double w = wave_sum(acc[q]);
-        if (lane == 0) red[wv][q] = w;
+        const double w = wave_sum63(acc[q]);
+        if (lane == 63) red[wv][q] = w;
       }
     }
     __syncthreads();
@@ -243,9 +240,9 @@ constexpr int PBS = 512;
 constexpr int PRPT = 4;
 
 __device__ __forceinline__ double block_sum8(double v, double* sh) {
-  v = wave_sum(v);
+  v = wave_sum63(v);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   return ((sh[0] + sh[1]) + (sh[2] + sh[3])) + ((sh[4] + sh[5]) + (sh[6] + sh[7]));
 }
@@ -289,8 +286,8 @@ __device__ __forceinline__ void panel_step(float (&P)[PRPT][NB], int j0, int m, 
 #pragma unroll
   for (int q = 0; q < NB - 1; ++q) {
     if (q < kb - 1) {
-      const double w = wave_sum((double)acc[q]);
-      if (lane == 0) red[wv][q] = w;
+      const double w = wave_sum63((double)acc[q]);
+      if (lane == 63) red[wv][q] = w;
     }
   }
   __syncthreads();
@@ -451,8 +448,8 @@ __device__ __forceinline__ void coop_step(float (&P)[PRPT][NB], int j0, int m, i
     }
 #pragma unroll
     for (int q = 0; q < NB - 1; ++q) {
-      const double w = wave_sum((double)acc[q]);
-      if (lane == 0) L.red[wv][q] = w;
+      const double w = wave_sum63((double)acc[q]);
+      if (lane == 63) L.red[wv][q] = w;
     }
     __syncthreads();
     if (tid < kb - 1)

@@ -25,14 +25,18 @@ __device__ __forceinline__ double lane63(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-__device__ __forceinline__ double wave_sum_dpp(double v) {
+// the wave's total in lane 63 (the other lanes hold partial sums)
+__device__ __forceinline__ double wave_sum63(double v) {
   v += dpp_take<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]: pairs
   v += dpp_take<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]: quads
   v += dpp_take<0x141, 0xf>(v);  // row_half_mirror: 8 lanes
   v += dpp_take<0x140, 0xf>(v);  // row_mirror: 16 lanes
   v += dpp_take<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
   v += dpp_take<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
-  return lane63(v);
+  return v;
 }
+
+__device__ __forceinline__ double wave_sum_dpp(double v) { return lane63(wave_sum63(v)); }
+
 
 }  // namespace spaqr
