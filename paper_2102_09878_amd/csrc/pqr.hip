@@ -47,12 +47,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // block-wide argmax of (val, idx): larger val wins, lowest idx on ties
 __device__ __forceinline__ void block_argmax(double& bv, int& bi, double* shv, int* shi) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(bv, o, 64);
-    const int oi = __shfl_xor(bi, o, 64);
-    if (ov > bv || (ov == bv && oi < bi)) bv = ov, bi = oi;
-  }
+  wave_argmax_dpp(bv, bi);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) shv[threadIdx.x >> 6] = bv, shi[threadIdx.x >> 6] = bi;
   __syncthreads();
@@ -484,14 +479,7 @@ __device__ __forceinline__ bool keep_waiting(long long& spins, int* err) {
 }
 
 // wave argmax of (val, idx): larger val wins, lowest idx on ties
-__device__ __forceinline__ void wave_argmax(double& bv, int& bi) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(bv, o, 64);
-    const int oi = __shfl_xor(bi, o, 64);
-    if (ov > bv || (ov == bv && oi < bi)) bv = ov, bi = oi;
-  }
-}
+__device__ __forceinline__ void wave_argmax(double& bv, int& bi) { wave_argmax_dpp(bv, bi); }
 
 template <typename T, int PQ, int NCW>
 __global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, const int2* __restrict__ bmap,

@@ -39,4 +39,28 @@ __device__ __forceinline__ double wave_sum63(double v) {
 __device__ __forceinline__ double wave_sum_dpp(double v) { return lane63(wave_sum63(v)); }
 
 
+// (v, i) with the largest v, lowest i on ties, over the wave, returned to
+// all lanes.  Rows outside a step's mask see (-1, INT_MAX), which loses to
+// every candidate (values are norms, >= 0, or -1 for none).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ void amax_take(double& v, int& i) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)0xBFF00000, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+  const int oi = __builtin_amdgcn_update_dpp(0x7fffffff, i, CTRL, ROWMASK, 0xf, false);
+  const double ov = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  if (ov > v || (ov == v && oi < i)) v = ov, i = oi;
+}
+
+__device__ __forceinline__ void wave_argmax_dpp(double& v, int& i) {
+  amax_take<0xB1, 0xf>(v, i);
+  amax_take<0x4E, 0xf>(v, i);
+  amax_take<0x141, 0xf>(v, i);
+  amax_take<0x140, 0xf>(v, i);
+  amax_take<0x142, 0xa>(v, i);
+  amax_take<0x143, 0xc>(v, i);
+  v = lane63(v);
+  i = __builtin_amdgcn_readlane(i, 63);
+}
+
 }  // namespace spaqr
