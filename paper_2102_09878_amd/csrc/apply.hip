@@ -53,7 +53,7 @@ __device__ void trsv_upper(const T* __restrict__ R, int64_t ld, int n, double* t
       double v = lane < nb ? t[jb + lane] : 0.0;
       for (int c = nb - 1; c >= 0; --c) {
         if (lane == c) v = v / (double)Ds[c][c];
-        const double tj = __shfl(v, c, 64);
+        const double tj = lane_bcast(v, c);
         if (lane < c) v -= tj * (double)Ds[c][lane];
       }
       if (lane < nb) t[jb + lane] = v;
@@ -95,7 +95,7 @@ __device__ void trsv_upper_t(const T* __restrict__ R, int64_t ld, int n, double*
       double v = lane < nb ? t[jb + lane] : 0.0;
       for (int c = 0; c < nb; ++c) {
         if (lane == c) v = v / (double)Ds[c][c];
-        const double yj = __shfl(v, c, 64);
+        const double yj = lane_bcast(v, c);
         if (lane > c && lane < nb) v -= (double)Ds[lane][c] * yj;
       }
       if (lane < nb) t[jb + lane] = v;

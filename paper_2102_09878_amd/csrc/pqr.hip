@@ -328,7 +328,7 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
         }
       dot = wave_sum(dot);
       const double f = tv * dot;
-      const double yi = __shfl(yv[k][0], i - i0, 64) - f;
+      const double yi = lane_bcast(yv[k][0], i - i0) - f;
       if (tv != 0.0)
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
@@ -673,7 +673,7 @@ __global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, c
 #pragma unroll
       for (int w = 0; w < 4; ++w) part[w] = wave_sum(part[w]);
       const double xn2 = (part[0] + part[1]) + (part[2] + part[3]);
-      const double alpha = __shfl(xs[0], 0, 64);
+      const double alpha = lane_bcast(xs[0], 0);
       house_scalars(alpha, xn2, beta, tv, scal);
       if (i == 0) r00 = fabs(beta);
       stop = fabs(beta) <= floor_v;
@@ -741,7 +741,7 @@ __global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, c
     T myyold = T(0);
 #pragma unroll
     for (int k = 0; k < NCW; ++k) {
-      const T yk = __shfl(yold[k], i & 63, 64);
+      const T yk = lane_bcast(yold[k], i & 63);
       if (lane == k) mydot = dot[k], myyold = yk;
     }
     if (tv != 0.0)
