@@ -135,9 +135,8 @@ __global__ __launch_bounds__(BS) void k_pqr_init(const PQRDesc* __restrict__ D,
 }
 
 // PQ: rows per lane held in registers for this work-group's columns (the
-// launcher picks 2 to 5 when that covers the batch's tallest matrix from
-// the step's 64-aligned row window; 0 keeps the columns in memory, which
-// measured faster for taller ones).
+// launcher picks 2 to 16 when that covers the batch's tallest matrix from
+// the step's 64-aligned row window; 0 keeps the columns in memory).
 // NC = cw / 4 columns per wave.
 // Optional self-timing: when stamp is set, thread 0 of every work-group
 // folds the complement of the real-time counter into its slot's first word
@@ -211,7 +210,7 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
   int jcol[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) jcol[k] = c0 + wv + 4 * k;
-  double yv[NC][PQ > 0 ? PQ : 1];
+  T yv[NC][PQ > 0 ? PQ : 1];  // values of the storage type (exactly what memory holds)
   double v1p[NC], v2p[NC], dnp[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) v1p[k] = 0.0, v2p[k] = 1.0, dnp[k] = 1.0;
@@ -223,7 +222,7 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
 #pragma unroll
       for (int q = 0; q < PQ; ++q) {
         const int r = i0 + lane + 64 * q;
-        yv[k][q] = (r >= i && r < m) ? (double)y[r] : 0.0;
+        yv[k][q] = (r >= i && r < m) ? y[r] : T(0);
       }
       dnp[k] = done[j];
       v1p[k] = vn1[j];
@@ -324,19 +323,19 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
           const int r = i0 + lane + 64 * q;
-          if (r >= i && r < m) dot += x[r - i] * yv[k][q];
+          if (r >= i && r < m) dot += x[r - i] * (double)yv[k][q];
         }
       dot = wave_sum(dot);
       const double f = tv * dot;
-      const double yi = lane_bcast(yv[k][0], i - i0) - f;
+      const double yi = (double)lane_bcast(yv[k][0], i - i0) - f;
       if (tv != 0.0)
 #pragma unroll
         for (int q = 0; q < PQ; ++q) {
           const int r = i0 + lane + 64 * q;
           if (r >= i && r < m) {
-            const T nv = static_cast<T>(yv[k][q] - f * x[r - i]);
+            const T nv = static_cast<T>((double)yv[k][q] - f * x[r - i]);
             y[r] = nv;
-            yv[k][q] = (double)nv;
+            yv[k][q] = nv;
           }
         }
       const double v1 = v1p[k];
@@ -351,7 +350,7 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
 #pragma unroll
           for (int q = 0; q < PQ; ++q) {
             const int r = i0 + lane + 64 * q;
-            if (r > i && r < m) s2 += yv[k][q] * yv[k][q];
+            if (r > i && r < m) s2 += (double)yv[k][q] * (double)yv[k][q];
           }
           s2 = sqrt(wave_sum(s2));
           if (lane == 0) vn1[j] = s2, vn2[j] = s2;
@@ -852,6 +851,14 @@ void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRSta
       SPAQR_PQR_GO(4, PQR_CW / 4);
     else if (rows <= 320)
       SPAQR_PQR_GO(5, PQR_CW / 4);
+    else if (rows <= 384)
+      SPAQR_PQR_GO(6, PQR_CW / 4);
+    else if (rows <= 512)
+      SPAQR_PQR_GO(8, PQR_CW / 4);
+    else if (rows <= 768)
+      SPAQR_PQR_GO(12, PQR_CW / 4);
+    else if (rows <= 1024)
+      SPAQR_PQR_GO(16, PQR_CW / 4);
     else
       SPAQR_PQR_GO(0, PQR_CW / 4);
   } else {
