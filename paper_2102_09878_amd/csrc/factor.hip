@@ -560,7 +560,7 @@ class Factorizer {
     ws.tbuf = scratch(qrpool_, 0, nf * QR_NB * QR_NB);
     ws.betas = scratch(qrpool_, 1, nf);
     ws.normp = scratch(qrpool_, 2, nf * ws.MS);
-    ws.dp = scratch(qrpool_, 3, nf * ws.MS * QR_NB);
+    ws.dp = scratch(qrpool_, 3, 2 * nf * ws.MS * QR_NB);
     ws.gp = scratch(qrpool_, 4, nf * ws.MS * QR_NB * QR_NB);
     ws.wp = scratch(qrpool_, 5, nf * ws.MT * ws.MS * QR_NB * QR_TN);
     ws.w = scratch(qrpool_, 6, nf * ws.MT * QR_NB * QR_TN);

@@ -256,32 +256,24 @@ __device__ __forceinline__ void panel_step(float (&P)[PRPT][NB], int j0, int m, 
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int c = j0 + I;
   const int oc = I % PBS, kc = I / PBS;
+  // one pass over the rows below c: ||x||^2 and x^T A[c+1:, q] for the other
+  // panel columns (x = A[c+1:, c], not yet scaled), reduced together; a
+  // thread sums its (at most PRPT) rows in FP32, the reduction is FP64
   double part = 0.0;
-#pragma unroll
-  for (int k = 0; k < PRPT; ++k) {
-    const int r = j0 + tid + PBS * k;
-    if (r > c && r < m) part += (double)P[k][I] * (double)P[k][I];
-    if (tid == oc && k == kc)
-#pragma unroll
-      for (int q = 0; q < NB; ++q) rowc[q] = P[k][q];
-  }
-  const double xn2 = block_sum8(part, sh);
-  const double alpha = rowc[I];
-  double beta, tv, scal;
-  house_scalars(alpha, xn2, beta, tv, scal);
-  const double tvT = (double)static_cast<float>(tv);
-  // a thread sums its (at most PRPT) rows in FP32, the reduction is FP64
   float acc[NB - 1];
 #pragma unroll
   for (int q = 0; q < NB - 1; ++q) acc[q] = 0.0f;
 #pragma unroll
   for (int k = 0; k < PRPT; ++k) {
     const int r = j0 + tid + PBS * k;
-    if (r <= c || r >= m) continue;
-    if (tv != 0.0) P[k][I] = static_cast<float>(P[k][I] * scal);
-    const float vi = P[k][I];
+    if (tid == oc && k == kc)
 #pragma unroll
-    for (int q = 0; q < NB - 1; ++q) acc[q] = fmaf(vi, P[k][q < I ? q : q + 1], acc[q]);
+      for (int q = 0; q < NB; ++q) rowc[q] = P[k][q];
+    if (r <= c || r >= m) continue;
+    const float xi = P[k][I];
+    part += (double)xi * (double)xi;
+#pragma unroll
+    for (int q = 0; q < NB - 1; ++q) acc[q] = fmaf(xi, P[k][q < I ? q : q + 1], acc[q]);
   }
 #pragma unroll
   for (int q = 0; q < NB - 1; ++q) {
@@ -290,16 +282,24 @@ __device__ __forceinline__ void panel_step(float (&P)[PRPT][NB], int j0, int m, 
       if (lane == 63) red[wv][q] = w;
     }
   }
+  part = wave_sum63(part);
+  if (lane == 63) red[wv][NB - 1] = part;
   __syncthreads();
-  if (tid < kb - 1)
+  if (tid < kb - 1 || tid == NB - 1)
     sv[tid] = ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) +
               ((red[4][tid] + red[5][tid]) + (red[6][tid] + red[7][tid]));
   __syncthreads();
+  const double xn2 = sv[NB - 1];
+  const double alpha = rowc[I];
+  double beta, tv, scal;
+  house_scalars(alpha, xn2, beta, tv, scal);
+  const double tvT = (double)static_cast<float>(tv);
   if (tid < kb - 1) {
+    const double svq = tv != 0.0 ? scal * sv[tid] : sv[tid];
     if (tid < I)
-      gcol[tid] = sv[tid] + rowc[tid];
+      gcol[tid] = svq + rowc[tid];
     else
-      fj[tid + 1] = tv * (sv[tid] + rowc[tid + 1]);
+      fj[tid + 1] = tv * (svq + rowc[tid + 1]);
   }
   __syncthreads();
   if (tid < I) {
@@ -313,13 +313,14 @@ __device__ __forceinline__ void panel_step(float (&P)[PRPT][NB], int j0, int m, 
   for (int k = 0; k < PRPT; ++k) {
     const int r = j0 + tid + PBS * k;
     if (r < c || r >= m) continue;
-    const double vi = P[k][I];
     if (r == c) {
 #pragma unroll
       for (int q = I + 1; q < NB; ++q)
         if (q < kb && tv != 0.0) P[k][q] = static_cast<float>((double)P[k][q] - fj[q]);
       P[k][I] = static_cast<float>(beta);
     } else if (tv != 0.0) {
+      P[k][I] = static_cast<float>(P[k][I] * scal);
+      const double vi = P[k][I];
 #pragma unroll
       for (int q = I + 1; q < NB; ++q)
         if (q < kb) P[k][q] = static_cast<float>((double)P[k][q] - fj[q] * vi);
@@ -405,35 +406,20 @@ struct CoopShared {
 
 template <int I>
 __device__ __forceinline__ void coop_step(float (&P)[PRPT][NB], int j0, int m, int kb, int rbase, int sg, int S,
-                                          float* tau, double* normp, double* dp, double* rowc_g, CoopShared& L) {
+                                          float* tau, double* dpb, double* rowc_g, CoopShared& L) {
   namespace cg = cooperative_groups;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const bool work = I < kb;
   const int c = j0 + I;
   double* rowc_i = rowc_g + (I & 1) * NB;
-  // phase 1: segment partial of ||A[c+1:, c]||^2; row c lives in segment 0, thread I, slot 0
-  double part = 0.0;
+  // Column I's partials, double-buffered by column parity: slots 0 .. NB-2
+  // hold x^T A[c+1:, q] of the other panel columns (x = A[c+1:, c], not yet
+  // scaled), slot NB-1 holds ||x||^2, so one grid barrier serves both sums.
+  // (A buffer is rewritten two columns later, after every work-group has
+  // passed the barrier in between and so has read it.)
+  double* dp = dpb + (I & 1) * S * NB;
   if (work) {
-#pragma unroll
-    for (int k = 0; k < PRPT; ++k) {
-      const int r = rbase + tid + PBS * k;
-      if (r > c && r < m) part += (double)P[k][I] * (double)P[k][I];
-    }
-    if (sg == 0 && tid == I)
-#pragma unroll
-      for (int q = 0; q < NB; ++q) rowc_i[q] = P[0][q];
-  }
-  part = block_sum8(part, L.sh);
-  if (work && tid == 0) normp[sg] = part;
-  cg::this_grid().sync();
-  // phase 2: reflector scalars (identical in every segment), scale, dot partials
-  double beta = 0.0, tv = 0.0, scal = 1.0;
-  if (work) {
-    double xn2 = 0.0;
-    for (int t = 0; t < S; ++t) xn2 += normp[t];
-    if (tid < NB) L.rowc[tid] = rowc_i[tid];
-    __syncthreads();
-    house_scalars(L.rowc[I], xn2, beta, tv, scal);
+    double part = 0.0;
     float acc[NB - 1];
 #pragma unroll
     for (int q = 0; q < NB - 1; ++q) acc[q] = 0.0f;
@@ -441,36 +427,46 @@ __device__ __forceinline__ void coop_step(float (&P)[PRPT][NB], int j0, int m, i
     for (int k = 0; k < PRPT; ++k) {
       const int r = rbase + tid + PBS * k;
       if (r <= c || r >= m) continue;
-      if (tv != 0.0) P[k][I] = static_cast<float>(P[k][I] * scal);
-      const float vi = P[k][I];
+      const float xi = P[k][I];
+      part += (double)xi * (double)xi;
 #pragma unroll
-      for (int q = 0; q < NB - 1; ++q) acc[q] = fmaf(vi, P[k][q < I ? q : q + 1], acc[q]);
+      for (int q = 0; q < NB - 1; ++q) acc[q] = fmaf(xi, P[k][q < I ? q : q + 1], acc[q]);
     }
+    // row c lives in segment 0, thread I, slot 0
+    if (sg == 0 && tid == I)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) rowc_i[q] = P[0][q];
 #pragma unroll
     for (int q = 0; q < NB - 1; ++q) {
       const double w = wave_sum63((double)acc[q]);
       if (lane == 63) L.red[wv][q] = w;
     }
+    part = wave_sum63(part);
+    if (lane == 63) L.red[wv][NB - 1] = part;
     __syncthreads();
-    if (tid < kb - 1)
+    if (tid < kb - 1 || tid == NB - 1)
       dp[sg * NB + tid] = ((L.red[0][tid] + L.red[1][tid]) + (L.red[2][tid] + L.red[3][tid])) +
                           ((L.red[4][tid] + L.red[5][tid]) + (L.red[6][tid] + L.red[7][tid]));
   }
   cg::this_grid().sync();
-  // phase 3: sums over the segments, T column, update of the owned rows
+  // reflector scalars (identical in every segment), sums over the segments,
+  // T column, update of the owned rows
   if (work) {
+    double xn2 = 0.0;
+    for (int t = 0; t < S; ++t) xn2 += dp[t * NB + NB - 1];
+    if (tid < NB) L.rowc[tid] = rowc_i[tid];
+    __syncthreads();
+    double beta, tv, scal;
+    house_scalars(L.rowc[I], xn2, beta, tv, scal);
     const double tvT = (double)static_cast<float>(tv);
     if (tid < kb - 1) {
       double a = 0.0;
       for (int t = 0; t < S; ++t) a += dp[t * NB + tid];
-      L.sv[tid] = a;
-    }
-    __syncthreads();
-    if (tid < kb - 1) {
+      const double sv = tv != 0.0 ? scal * a : a;
       if (tid < I)
-        L.gcol[tid] = L.sv[tid] + L.rowc[tid];
+        L.gcol[tid] = sv + L.rowc[tid];
       else
-        L.fj[tid + 1] = tv * (L.sv[tid] + L.rowc[tid + 1]);
+        L.fj[tid + 1] = tv * (sv + L.rowc[tid + 1]);
     }
     __syncthreads();
     if (tid < I) {
@@ -484,13 +480,14 @@ __device__ __forceinline__ void coop_step(float (&P)[PRPT][NB], int j0, int m, i
     for (int k = 0; k < PRPT; ++k) {
       const int r = rbase + tid + PBS * k;
       if (r < c || r >= m) continue;
-      const double vi = P[k][I];
       if (r == c) {
 #pragma unroll
         for (int q = I + 1; q < NB; ++q)
           if (q < kb && tv != 0.0) P[k][q] = static_cast<float>((double)P[k][q] - L.fj[q]);
         P[k][I] = static_cast<float>(beta);
       } else if (tv != 0.0) {
+        P[k][I] = static_cast<float>(P[k][I] * scal);
+        const double vi = P[k][I];
 #pragma unroll
         for (int q = I + 1; q < NB; ++q)
           if (q < kb) P[k][q] = static_cast<float>((double)P[k][q] - L.fj[q] * vi);
@@ -505,12 +502,11 @@ __device__ __forceinline__ void coop_step(float (&P)[PRPT][NB], int j0, int m, i
 // and reaches every grid barrier.
 template <int I>
 __device__ __forceinline__ void coop_steps(float (&P)[PRPT][NB], int j0, int m, int kb, int kbmax, int rbase, int sg,
-                                           int S, float* tau, double* normp, double* dp, double* rowc_g,
-                                           CoopShared& L) {
+                                           int S, float* tau, double* dp, double* rowc_g, CoopShared& L) {
   if constexpr (I < NB) {
     if (I >= kbmax) return;
-    coop_step<I>(P, j0, m, kb, rbase, sg, S, tau, normp, dp, rowc_g, L);
-    coop_steps<I + 1>(P, j0, m, kb, kbmax, rbase, sg, S, tau, normp, dp, rowc_g, L);
+    coop_step<I>(P, j0, m, kb, rbase, sg, S, tau, dp, rowc_g, L);
+    coop_steps<I + 1>(P, j0, m, kb, kbmax, rbase, sg, S, tau, dp, rowc_g, L);
   }
 }
 
@@ -535,8 +531,8 @@ __global__ __launch_bounds__(PBS) void k_qrp_coop(const QRDesc* __restrict__ D, 
   }
   for (int e = tid; e < NB * NB; e += PBS) L.Ts[e / NB][e % NB] = 0.0;
   __syncthreads();
-  coop_steps<0>(P, j0, m, kb, kbmax, rbase, sg, S, static_cast<float*>(d.tau), ws.normp + (int64_t)f * ws.MS,
-                ws.dp + (int64_t)f * ws.MS * NB, ws.gp + (int64_t)f * ws.MS * NB * NB, L);
+  coop_steps<0>(P, j0, m, kb, kbmax, rbase, sg, S, static_cast<float*>(d.tau), ws.dp + (int64_t)f * 2 * ws.MS * NB,
+                ws.gp + (int64_t)f * ws.MS * NB * NB, L);
 #pragma unroll
   for (int k = 0; k < PRPT; ++k) {
     const int r = rbase + tid + PBS * k;

@@ -301,7 +301,7 @@ struct QRWork {
   double* tbuf;   // nfront * NB * NB        compact-WY T factors
   double* betas;  // nfront                  last diagonal of a row-split panel
   double* normp;  // nfront * MS             norm partials
-  double* dp;     // nfront * MS * NB        dot partials
+  double* dp;     // 2 * nfront * MS * NB    dot partials (two column parities in the cooperative panel)
   double* gp;     // nfront * MS * NB * NB   Gram partials
   double* wp;     // nfront * MT * MS * NB * TN  partial V^T C
   double* w;      // nfront * MT * NB * TN        reduced T^T V^T C
