@@ -61,27 +61,22 @@ __global__ __launch_bounds__(BS) void k_gather(const GatherDesc* __restrict__ D)
   const int c1 = min(d.ncols, c0 + GATHER_COLS);
   const T* src = static_cast<const T*>(d.src);
   T* dst = static_cast<T*>(d.dst);
-  if (!d.transpose) {
-    for (int c = c0; c < c1; ++c) {
-      const int sc = d.colmap[c];
-      T* out = dst + d.row0 + (d.col0 + c) * d.dst_ld;
-      if (sc >= 0) {
-        const T* in = src + (int64_t)sc * d.src_ld;
-        for (int r = threadIdx.x; r < d.nrows; r += BS) out[r] = in[r];
-      } else {
-        for (int r = threadIdx.x; r < d.nrows; r += BS) out[r] = T(0);
-      }
-    }
-  } else {
-    for (int c = c0; c < c1; ++c) {
-      const int sc = d.colmap[c];
-      T* out = dst + c + d.col0 * d.dst_ld;
-      if (sc >= 0) {
-        const T* in = src + (int64_t)sc * d.src_ld;
-        for (int r = threadIdx.x; r < d.nrows; r += BS) out[r * d.dst_ld] = in[r];
-      } else {
-        for (int r = threadIdx.x; r < d.nrows; r += BS) out[r * d.dst_ld] = T(0);
-      }
+  // a thread's rows of all the block's columns are loaded before any store
+  int sc[GATHER_COLS];
+#pragma unroll
+  for (int u = 0; u < GATHER_COLS; ++u) sc[u] = c0 + u < c1 ? d.colmap[c0 + u] : -1;
+  for (int r = threadIdx.x; r < d.nrows; r += BS) {
+    T v[GATHER_COLS];
+#pragma unroll
+    for (int u = 0; u < GATHER_COLS; ++u) v[u] = sc[u] >= 0 ? src[r + (int64_t)sc[u] * d.src_ld] : T(0);
+    if (!d.transpose) {
+#pragma unroll
+      for (int u = 0; u < GATHER_COLS; ++u)
+        if (c0 + u < c1) dst[d.row0 + r + (d.col0 + c0 + u) * d.dst_ld] = v[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < GATHER_COLS; ++u)
+        if (c0 + u < c1) dst[c0 + u + (d.col0 + r) * d.dst_ld] = v[u];
     }
   }
 }
@@ -215,10 +210,20 @@ __global__ __launch_bounds__(BS) void k_owner(const OwnerDesc* __restrict__ D) {
   double bv = -1.0;
   if (r < nrows)
     for (int q = wv; q < d.ncl; q += 4) {
+      // 16 columns per pass: indices, then entries, then the sum in column order
+      const int cb = d.cl_off[q], ce = d.cl_off[q + 1];
       double s = 0.0;
-      for (int c = d.cl_off[q]; c < d.cl_off[q + 1]; ++c) {
-        const double v = A[r + (int64_t)d.colmap[c] * d.lda];
-        s += v * v;
+#pragma unroll 1
+      for (int c = cb; c < ce; c += 16) {
+        int cm[16];
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) cm[u] = d.colmap[min(c + u, ce - 1)];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = A[r + (int64_t)cm[u] * d.lda];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (c + u < ce) s += (double)v[u] * (double)v[u];
       }
       if (s > bv) bv = s, best = q;
     }
