@@ -165,13 +165,40 @@ __global__ __launch_bounds__(BS) void k_apply(const ApplyOp* __restrict__ ops, i
       // one wave: a lane owns entries lane, lane + 64, ..., so the
       // reflectors need no barrier, only a wave reduction each
       if (tid < 64) {
-        for (int s = 0; s < r; ++s) {
+        // lane l takes rows k + l + 64 j of reflector k; the next reflector's
+        // entries (and tau) are loaded while the current one is applied
+        T vn[4];
+        T taun = T(0);
+        auto fetch = [&](int s, T (&v4)[4], T& tk) {
           const int k = transpose ? s : r - 1 - s;
           const T* v = R + (int64_t)k * op.ld;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int i = k + tid + 64 * j;
+            v4[j] = i < n1 ? v[i] : T(0);
+          }
+          tk = tau[k];
+        };
+        if (r > 0) fetch(0, vn, taun);
+        for (int s = 0; s < r; ++s) {
+          const int k = transpose ? s : r - 1 - s;
+          T vc[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) vc[j] = vn[j];
+          const T tk = taun;
+          if (s + 1 < r) fetch(s + 1, vn, taun);
           double part = 0.0;
-          for (int i = k + tid; i < n1; i += 64) part += (double)v[i] * t[i];
-          const double f = (double)tau[k] * wave_sum(part);
-          for (int i = k + tid; i < n1; i += 64) t[i] -= f * (double)v[i];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int i = k + tid + 64 * j;
+            if (i < n1) part += (double)vc[j] * t[i];
+          }
+          const double f = (double)tk * wave_sum(part);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int i = k + tid + 64 * j;
+            if (i < n1) t[i] -= f * (double)vc[j];
+          }
         }
       }
       __syncthreads();
@@ -219,8 +246,19 @@ __global__ __launch_bounds__(BS) void k_apply_gemv(const ApplyOp* __restrict__ o
     for (int ib = 0; ib < n1; ib += (rows >= BS ? BS : rows)) {
       const int i = ib + (rows >= BS ? tid : i0);
       double acc = 0.0;
-      if (sl < ns && i < n1)
-        for (int c = c0 + sl; c < c1; c += ns) acc += (double)RN[i + (int64_t)c * op.ld] * v[c - c0];
+      if (sl < ns && i < n1) {
+        // 16 columns' loads issued ahead of their sums (columns in the same order)
+        const T* ri = RN + i;
+#pragma unroll 1
+        for (int c = c0 + sl; c < c1; c += 16 * ns) {
+          T rv[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) rv[u] = ri[(int64_t)min(c + u * ns, c1 - 1) * op.ld];
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            if (c + u * ns < c1) acc += (double)rv[u] * v[c + u * ns - c0];
+        }
+      }
       if (ns == 1) {
         if (sl == 0 && i < n1) out[i] = acc;
       } else {
