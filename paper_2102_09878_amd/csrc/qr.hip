@@ -239,14 +239,6 @@ __global__ __launch_bounds__(BS) void k_qr_panel(const QRDesc* __restrict__ D, i
 constexpr int PBS = 512;
 constexpr int PRPT = 4;
 
-__device__ __forceinline__ double block_sum8(double v, double* sh) {
-  v = wave_sum63(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  return ((sh[0] + sh[1]) + (sh[2] + sh[3])) + ((sh[4] + sh[5]) + (sh[6] + sh[7]));
-}
-
 // One column step of the register panel; I is a compile-time column so all
 // register indexing is static.
 template <int I>
