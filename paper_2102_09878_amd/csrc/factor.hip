@@ -507,6 +507,10 @@ class Factorizer {
     }
     const PQRDesc* d = upload(q);
     const int2* dmap = upload(bmap);
+    std::vector<PQRDesc> qb;
+    qb.reserve(bmap.size());
+    for (const int2& b : bmap) qb.push_back(q[b.x]);
+    const PQRDesc* dblk = upload(qb);
     auto* states = static_cast<PQRState*>(H.arena.alloc(2 * q.size() * sizeof(PQRState)));
     auto* parts = static_cast<PQRPart*>(H.arena.alloc(2 * (size_t)total * sizeof(PQRPart)));
     auto* frop = static_cast<double*>(H.arena.alloc((size_t)total * sizeof(double)));
@@ -527,7 +531,7 @@ class Factorizer {
       const bool timed = H.kt.pick("pqr_step");
       unsigned long long* stamp = timed ? H.kt.stamp(st) : nullptr;
       if (timed) timed_steps_.push_back(steps);
-      launch_pqr_step<T>(d, total, total, states, parts, frop, dmap, active, steps, eps_, max_m, cw, stamp, st);
+      launch_pqr_step<T>(dblk, total, total, states, parts, frop, dmap, active, steps, eps_, max_m, cw, stamp, st);
       ++launches_;
       ++steps;
       if (steps % 16 == 0 && steps < kmax) {

@@ -166,13 +166,12 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
   __shared__ double shv[4];
   __shared__ int shi[4];
   // Loads are issued in the order they are needed (they complete in
-  // order): block map with the first descriptor (most batches of single
-  // large matrices need no second round trip), state and chunk partials,
-  // then this work-group's own columns, which are consumed last.
+  // order): block map with this work-group's own copy of its matrix's
+  // descriptor (no second round trip to find it), state and chunk
+  // partials, then the work-group's own columns, which are consumed last.
   const int2 bm = bmap[blockIdx.x];
-  const PQRDesc d0 = D[0];
+  const PQRDesc d = D[blockIdx.x];
   const int mi = bm.x, ch = bm.y;
-  const PQRDesc d = mi == 0 ? d0 : D[mi];
   const PQRState sp = S[2 * mi + (i & 1)];
   PQRState* sn = S + 2 * mi + ((i + 1) & 1);
   const PQRPart* prd = parts + (size_t)(i & 1) * total_parts;
@@ -832,7 +831,7 @@ void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPa
 }
 
 template <typename T>
-void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRState* states,
+void launch_pqr_step(const PQRDesc* d_blk, int nblocks, int total_parts, PQRState* states,
                      PQRPart* parts, const double* frop, const int2* bmap, int* active, int i, double eps,
                      int max_m, int cw, unsigned long long* stamp, hipStream_t s) {
   if (nblocks <= 0) return;
@@ -840,7 +839,7 @@ void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRSta
   if (lds > 64 * 1024) throw Error(SPAQR_EARG, "rank-revealing QR block taller than 8192 rows");
   const int rows = max_m - (i & ~63);
 #define SPAQR_PQR_GO(Q, C)                                                                                   \
-  hipLaunchKernelGGL((k_pqr_step<T, Q, C>), dim3(nblocks), dim3(BS), lds, s, d_desc, states, parts, total_parts, \
+  hipLaunchKernelGGL((k_pqr_step<T, Q, C>), dim3(nblocks), dim3(BS), lds, s, d_blk, states, parts, total_parts,  \
                      frop, bmap, active, i, eps, stamp)
   if (cw == PQR_CW) {
     if (rows <= 128)

@@ -315,7 +315,9 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h_desc, const QR
 // chunks of PQR_CW over work-groups).  The caller provides device scratch:
 // states (2 per matrix), parts (2 per chunk), frop (squared Frobenius norm
 // per chunk, one per chunk), bmap (one int2 per chunk) and an `active`
-// counter; h_desc must already carry blk0/nblk.
+// counter; h_desc must already carry blk0/nblk.  The step launch takes one
+// descriptor per work-group (d_blk[b] = the descriptor of matrix bmap[b].x),
+// so a work-group finds its matrix without a dependent load.
 constexpr int PQR_CW = 8;
 // self-timing stamps of one timed launch: STAMP_SLOTS slots of STAMP_STRIDE
 // words (complement of the earliest start, latest end, padding)
@@ -325,7 +327,7 @@ template <typename T>
 void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPart* parts, double* frop,
                      const int2* bmap, hipStream_t s);
 template <typename T>
-void launch_pqr_step(const PQRDesc* d_desc, int nblocks, int total_parts, PQRState* states,
+void launch_pqr_step(const PQRDesc* d_blk, int nblocks, int total_parts, PQRState* states,
                      PQRPart* parts, const double* frop, const int2* bmap, int* active, int i, double eps, int max_m, int cw,
                      unsigned long long* stamp, hipStream_t s);
 template <typename T>
