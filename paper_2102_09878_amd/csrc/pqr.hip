@@ -311,6 +311,10 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
   }
   // apply H_i to the chunk's live columns and downdate their norms
   const double tol3z = sqrt(DBL_EPSILON);
+  // register path: the wave's best live column after the update (its norms
+  // are wave-uniform), so the chunk argmax needs no second read of them
+  double cv = -1.0;
+  int ci = INT_MAX;
   if (regs) {
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -338,6 +342,7 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
           }
         }
       const double v1 = v1p[k];
+      double nv1 = v1;
       if (v1 != 0.0) {
         const double ay = fabs((double)static_cast<T>(yi));
         double temp = 1.0 - (ay / v1) * (ay / v1);
@@ -352,11 +357,15 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
             if (r > i && r < m) s2 += (double)yv[k][q] * (double)yv[k][q];
           }
           s2 = sqrt(wave_sum(s2));
+          nv1 = s2;
           if (lane == 0) vn1[j] = s2, vn2[j] = s2;
-        } else if (lane == 0) {
-          vn1[j] = v1 * sqrt(temp);
+        } else {
+          nv1 = v1 * sqrt(temp);
+          if (lane == 0) vn1[j] = nv1;
         }
       }
+      // ascending columns: the first of equal norms wins, as in chunk_argmax
+      if (nv1 > cv) cv = nv1, ci = j;
     }
   }
   for (int j = c0 + wv; !regs && j < c1; j += 4) {
@@ -389,8 +398,19 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
     }
   }
   if (tid == 0 && p >= c0 && p < c1) done[p] = 1.0;
-  __syncthreads();
-  chunk_argmax(vn1, done, c0, c1, p, bv, bi, shv, shi);
+  if (regs) {
+    // every wave has passed the barriers after the pivot argmax's reads of
+    // shv / shi, so they can be reused here
+    if (lane == 0) shv[wv] = cv, shi[wv] = ci;
+    __syncthreads();
+    bv = shv[0];
+    bi = shi[0];
+    for (int w = 1; w < 4; ++w)
+      if (shv[w] > bv || (shv[w] == bv && shi[w] < bi)) bv = shv[w], bi = shi[w];
+  } else {
+    __syncthreads();
+    chunk_argmax(vn1, done, c0, c1, p, bv, bi, shv, shi);
+  }
   if (tid == 0) {
     PQRPart q;
     q.val = bv;
