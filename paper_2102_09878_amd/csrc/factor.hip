@@ -1044,7 +1044,10 @@ void Factorizer<T>::scale_all() {
   }
   int* dtp = upload(tp.v);
   for (size_t i = 0; i < td.size(); ++i) td[i].colmap = dtp + td_map[i];
-  launch_trsm<T>(upload(td), (int)td.size(), td_rows, td_c, st);
+  std::vector<int2> trb;
+  for (size_t i = 0; i < td.size(); ++i)
+    for (int b = 0; b * TRSM_ROWS < td[i].nrows; ++b) trb.push_back(make_int2((int)i, b));
+  launch_trsm<T>(upload(td), (int)td.size(), td_rows, td_c, upload(trb), (int)trb.size(), st);
   ++launches_;
   timer_end();
   // rank-deficiency flags are read together with the step-1 ranks

@@ -140,18 +140,20 @@ __global__ __launch_bounds__(BS) void k_trsm(const TrsmDesc* __restrict__ D) {
 // they are solved: B is read and written once, the left-looking updates
 // read the solved columns from LDS, and the current 16-column block of R is
 // staged in LDS.  One wave per work-group, thread = row.  Dynamic LDS:
-// c (64 + 1 + TRSM_NB) doubles for the largest c of the launch.
-constexpr int TRSM_ROWS = 64;
-
+// c (64 + 1 + TRSM_NB) doubles for the largest c of the launch.  The grid
+// is one work-group per (descriptor, 64-row block) pair that exists, listed
+// in bmap, so short descriptors of a launch start no idle work-groups.
 template <typename T>
-__global__ __launch_bounds__(TRSM_ROWS) void k_trsm_lds(const TrsmDesc* __restrict__ D, int cmax) {
+__global__ __launch_bounds__(TRSM_ROWS) void k_trsm_lds(const TrsmDesc* __restrict__ D,
+                                                        const int2* __restrict__ bmap, int cmax) {
   extern __shared__ double lds[];
-  const TrsmDesc d = D[blockIdx.x];
-  if ((int)blockIdx.y * TRSM_ROWS >= d.nrows) return;  // whole block
+  const int2 bm = bmap[blockIdx.x];
+  const TrsmDesc d = D[bm.x];
+  if (bm.y * TRSM_ROWS >= d.nrows) return;  // whole block (not listed by the launcher)
   double* Xs = lds;                                        // [c][TRSM_ROWS + 1]
   double* Rs = lds + (size_t)cmax * (TRSM_ROWS + 1);       // [c][TRSM_NB]
   const int lane = threadIdx.x;
-  const int r = blockIdx.y * TRSM_ROWS + lane;
+  const int r = bm.y * TRSM_ROWS + lane;
   const bool live = r < d.nrows;
   T* B = static_cast<T*>(d.B);
   const T* R = static_cast<const T*>(d.R);
@@ -328,7 +330,8 @@ void launch_scatter_csr(T* base, const int64_t* dst, const double* ahat, int64_t
 }
 
 template <typename T>
-void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, int max_c, hipStream_t s) {
+void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, int max_c, const int2* d_rowblocks,
+                 int n_rowblocks, hipStream_t s) {
   if (n <= 0 || max_rows <= 0) return;
   static int lds_cap = -1;
   if (lds_cap < 0) {
@@ -338,8 +341,8 @@ void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, int max_c, hipStre
   }
   const size_t lds = (size_t)max_c * (TRSM_ROWS + 1 + TRSM_NB) * sizeof(double);
   if (max_c > 0 && lds <= (size_t)lds_cap) {
-    hipLaunchKernelGGL(k_trsm_lds<T>, dim3(n, (max_rows + TRSM_ROWS - 1) / TRSM_ROWS), dim3(TRSM_ROWS), lds, s,
-                       d_desc, max_c);
+    if (n_rowblocks <= 0) return;
+    hipLaunchKernelGGL(k_trsm_lds<T>, dim3(n_rowblocks), dim3(TRSM_ROWS), lds, s, d_desc, d_rowblocks, max_c);
   } else {
     hipLaunchKernelGGL(k_trsm<T>, dim3(n, (max_rows + BS - 1) / BS), dim3(BS), 0, s, d_desc);
   }
@@ -378,7 +381,7 @@ void launch_scatter(const ScatterDesc* d_desc, int n, hipStream_t s) {
 #define SPAQR_INST(T)                                                                          \
   template void launch_gather<T>(const GatherDesc*, int, int, hipStream_t);                    \
   template void launch_scatter_csr<T>(T*, const int64_t*, const double*, int64_t, hipStream_t); \
-  template void launch_trsm<T>(const TrsmDesc*, int, int, int, hipStream_t);                        \
+  template void launch_trsm<T>(const TrsmDesc*, int, int, int, const int2*, int, hipStream_t);                        \
   template void launch_owner<T>(const OwnerDesc*, int, int, hipStream_t);                           \
   template void launch_rowcopy<T>(const RowCopyDesc*, int, int, hipStream_t);                         \
   template void launch_extract<T>(const ExtractDesc*, int, hipStream_t);                       \

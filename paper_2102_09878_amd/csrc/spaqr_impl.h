@@ -360,8 +360,12 @@ int pqr_run_width(int max_m, const std::vector<int>& ns, int* rows);
 template <typename T>
 void launch_pqr_run(const PQRDesc* d_desc, int nblocks, const int2* bmap, const PQRXch& xc, double eps, int cw,
                     unsigned long long* stamp, hipStream_t s);
+// rowblocks: (descriptor, block) for every TRSM_ROWS-row block of every
+// descriptor with rows (the LDS form launches one work-group per entry)
+constexpr int TRSM_ROWS = 64;
 template <typename T>
-void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, int max_c, hipStream_t s);
+void launch_trsm(const TrsmDesc* d_desc, int n, int max_rows, int max_c, const int2* d_rowblocks,
+                 int n_rowblocks, hipStream_t s);
 template <typename T>
 void launch_owner(const OwnerDesc* d_desc, int n, int max_rows, hipStream_t s);
 template <typename T>
