@@ -8,9 +8,10 @@ Follows Algorithm 1 of the paper (Section 2.7) step by step:
 * row matching + max-norm assignment of the unmatched rows (Section 2.2);
 * per level m = d .. 1:
     - block Householder elimination of every level-m cluster s; R_s goes to
-      W; the rows below the diagonal are compressed exactly and reassigned
-      to the neighbour cluster holding most of their squared norm (P_s,
-      Section 2.3);
+      W; the rows below the diagonal are compressed by a rank-revealing QR
+      (truncated by the rank rule on sparsified levels, exact on the others)
+      and reassigned to the neighbour cluster holding most of their squared
+      norm (P_s, Sections 2.3 and 4.2);
     - on sparsified levels: interface scaling A_pp = U_pp [R_pp; 0]
       (Section 2.4), sparsification step 1 (rank-revealing QR of the rows
       below the scaled diagonal, Section 2.5.1) on every interface, then
@@ -262,6 +263,8 @@ class _State:
         self.ledger = {k: [0.0, 0.0] for k in ("eliminate", "reassign", "scale", "sparsify", "merge")}
         self.stats = dict(aspect=[], ranks_step1=[], ranks_step2=[], rounds_elim=[], rounds_step2=[],
                           top_separator=None)
+        self.level = 0
+        self.log = None           # per rank-revealing QR records, when asked for (tests)
 
     # ---- helpers -------------------------------------------------------
     def sorted_live(self):
@@ -278,10 +281,16 @@ class _State:
             raise SpaqrError("forced rank list exhausted")
         return self.forced.pop(0)
 
-    def pivoted(self, C, kind):
+    def sparsified(self, level):
+        """Levels that are scaled and sparsified (Section 4: the first
+        leaf-side levels are skipped; the root has no interfaces left)."""
+        return 2 <= level <= self.an.depth - self.skip
+
+    def pivoted(self, C, kind, eps=None):
+        eps = self.eps if eps is None else eps
         forced = self.next_rank(None)
         if forced is None:
-            r, rows, perm, V, tau = dense.pivoted_qr(C, self.eps)
+            r, rows, perm, V, tau = dense.pivoted_qr(C, eps)
         else:
             r, rows, perm, V, tau = dense.pivoted_qr(C, 0.0)
             r = min(forced, r)
@@ -289,6 +298,10 @@ class _State:
             # rows beyond the forced rank must also be dropped from Q^T C
         self.ranks.append(r)
         m, n = C.shape
+        if self.log is not None:
+            self.log.append(dict(kind=kind, level=self.level, eps=eps, m=m, n=n, rank=r, rows=rows.copy(),
+                                 perm=perm.copy(), normf2=float(np.sum(C * C)),
+                                 forced=forced is not None))
         phase = "reassign" if kind == "reassign" else "sparsify"
         self.ledger[phase][0] += 4 * m * n * r - 2 * r * r * (m + n) + 4 * r ** 3 / 3 + 2 * m * n
         self.ledger[phase][1] += 8 * (m * n + r * n)
@@ -355,12 +368,15 @@ class _State:
             g.clus = set(N_s)
             g.role = ""
             r0 += g.nrows
-        # rows below the diagonal: exact compression, then reassignment (P_s)
+        # rows below the diagonal: compressed, then reassigned (P_s).  On a
+        # sparsified level they are sparsified like the interfaces (the
+        # reassign phase of Section 4.2); on the skipped leaf-side levels
+        # nothing is sparsified, so the compression is exact: the
+        # rank-revealing QR stops only at the numerical rank.
         if c_N > 0 and r_s > c_s:
-            # the rows below the diagonal are sparsified (rank-revealing QR,
-            # same rule as the interfaces) and the kept rows reassigned
             E = F[c_s:r_s, c_s:]
-            r, RE, V, tau = self.pivoted(E, "reassign")
+            eps_r = self.eps if self.sparsified(self.level) else 0.0
+            r, RE, V, tau = self.pivoted(E, "reassign", eps_r)
             ranges = []
             a = 0
             for c in N_s:
@@ -538,7 +554,7 @@ def _select_round(pending, conflict):
     return sel
 
 
-def factorize(an: Analysis, eps: float, skip: int, forced_ranks=None) -> Factor:
+def factorize(an: Analysis, eps: float, skip: int, forced_ranks=None, log=None) -> Factor:
     """Run Algorithm 1.
 
     Readings (the paper leaves these open):
@@ -554,19 +570,23 @@ def factorize(an: Analysis, eps: float, skip: int, forced_ranks=None) -> Factor:
       column with a cluster already taken in the round; likewise step 2 runs
       in rounds with p ~ q when q is among the columns of p's scaled rows or
       p among q's.  Inside a round the order does not change the result;
-    * rows below the diagonal of an eliminated cluster are sparsified before
-      they are reassigned (Section 4.2 describes the reassign phase this
-      way): a column-pivoted QR with the rank rule of Section 4 keeps the
-      leading rows of Q^T E, and each kept row goes to the neighbour cluster
-      with the largest sum of its squared entries.  Every rank-revealing QR
-      also stops at the numerical rank (|R_ii| <= 1000 u ||C||_F), where an
-      unpivoted or further-pivoted QR would be steered by rounding error;
+    * rows below the diagonal of an eliminated cluster are compressed by a
+      column-pivoted QR that keeps the leading rows of Q^T E, and each kept
+      row goes to the neighbour cluster with the largest sum of its squared
+      entries (ties to the lowest id).  On sparsified levels the rank rule
+      of Section 4 truncates it (Section 4.2 names the sparsification of
+      these rows as part of the reassign phase); on the leaf-side levels
+      where sparsification is skipped the compression is exact.  Every
+      rank-revealing QR also stops at the numerical rank
+      (|R_ii| <= 1000 u ||C||_F), where an unpivoted or further-pivoted QR
+      would be steered by rounding error;
     * scaling is applied to all interfaces of the level: every left
       transform U_pp^T first, then every right transform R_pp^-1;
     * step 2 compresses the column block of p over every row except p's
       own scaled rows, next to those scaled rows over the other columns.
     """
     st = _State(an, eps, skip, forced_ranks)
+    st.log = log
     st.stats["_rk2"] = []
     groups = initial_groups(an)
     for c in an.finest:
@@ -575,6 +595,7 @@ def factorize(an: Analysis, eps: float, skip: int, forced_ranks=None) -> Factor:
         st.live.add(c)
     d = an.depth
     for m in range(d, 0, -1):
+        st.level = m
         pending = sorted([c for c in st.live if c.sep.level == m], key=_key)
         if m == 1 and pending:
             st.stats["top_separator"] = (len(pending[0].slots), sum(g.nrows for g in pending[0].groups))
@@ -587,7 +608,7 @@ def factorize(an: Analysis, eps: float, skip: int, forced_ranks=None) -> Factor:
             pending = [s for s in pending if s not in sel]
             nrounds += 1
         st.stats["rounds_elim"].append((m, nrounds))
-        if 2 <= m <= d - skip and st.live:
+        if st.sparsified(m) and st.live:
             st.scale_all(m)
             st.step1_all(m)
             pending = st.sorted_live()
