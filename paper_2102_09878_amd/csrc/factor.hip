@@ -276,6 +276,10 @@ class Factorizer {
     return s;
   }
 
+  // Levels that are scaled and sparsified (Section 4: the first leaf-side
+  // levels are skipped, and the root has no interfaces left).
+  bool sparsified(int m) const { return m >= 2 && m <= P.depth - P.skip; }
+
   void sync() {
     SPAQR_HIP(hipStreamSynchronize(st));
     ++syncs_;
@@ -784,8 +788,12 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
       off += gr.nrows;
     }
     if (f.cN > 0 && f.rs > f.cs) {
-      // rows below the diagonal: sparsified by a rank-revealing QR in place
+      // rows below the diagonal: compressed by a rank-revealing QR in place,
+      // truncated by the eps rule on sparsified levels (the reassign phase
+      // of Section 4.2) and exact on the leaf-side levels that are not
+      // sparsified (Section 4: those levels skip sparsification)
       PQRDesc q{};
+      q.exact = sparsified(level_) ? 0 : 1;
       q.A = f.F + f.cs + (int64_t)f.cs * f.ld;
       q.lda = f.ld;
       q.m = f.rs - f.cs;
@@ -1510,7 +1518,7 @@ void Factorizer<T>::run() {
   for (int m = P.depth; m >= 1; --m) {
     level_ = m;
     eliminate_level(m);
-    if (m >= 2 && m <= P.depth - P.skip && !live.empty()) {
+    if (sparsified(m) && !live.empty()) {
       scale_all();
       step1_all();
       std::vector<int> pending(live.begin(), live.end());

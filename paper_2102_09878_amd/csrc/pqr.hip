@@ -16,8 +16,8 @@
 // one step later, after every work-group has read it.
 //
 // Rank rule (Section 4): stop at the first step whose |R_ii| is below
-// eps |R_00|, or at or below the numerical-rank floor noise * ||A||_F, or
-// when `forced` steps were taken.  Pivot ties go to the lowest column index.
+// eps |R_00| (unless the matrix is marked exact), or at or below the
+// numerical-rank floor noise * ||A||_F, or when `forced` steps were taken.  Pivot ties go to the lowest column index.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
     stop = fabs(beta) <= floor_v;
     if (d.forced >= 0)
       stop = stop || i >= d.forced;
-    else if (i > 0)
+    else if (i > 0 && !d.exact)
       stop = stop || fabs(beta) < eps * r00;
   }
   if (stop) {
@@ -439,10 +439,11 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
 // finished reading it.  The buffers are zeroed before the launch (tag 0 is
 // never current).  Matrices never wait on each other, and all waves of a
 // matrix reach the same stop decision at the same step.  Every wait is
-// bounded: past the spin limit a wave raises `err` and exits, and the others
-// exit when they see it.
+// bounded: past 100 ms a wave raises `err` and exits, and the others exit
+// when they see it.
 // ---------------------------------------------------------------------------
-constexpr long long PQR_SPIN = 1ll << 22;
+constexpr unsigned long long PQR_WAIT_TICKS = 10000000ull;  // 100 ms at 100 MHz
+constexpr int PQR_RUN_MAX_WAVES = 1000;
 constexpr int PQR_POLL = 8;  // chunk argmax words per lane and poll: matrices up to 512 chunks
 
 typedef unsigned long long u64;
@@ -485,13 +486,21 @@ struct Tagged<double> {
 
 __device__ __forceinline__ bool wave_all(bool ok) { return __ballot(!ok) == 0; }
 
-// Spin bookkeeping of one wait: false once the wait is abandoned.
-__device__ __forceinline__ bool keep_waiting(long long& spins, int* err) {
-  if (++spins > PQR_SPIN) {
+// Bookkeeping of one wait, bounded by elapsed time on the constant-rate
+// real-time counter (100 MHz): false once the wait is abandoned, after
+// PQR_WAIT_TICKS or as soon as another wave has raised `err`.
+struct WaitClock {
+  unsigned long long t0 = 0;
+  unsigned polls = 0;
+};
+__device__ __forceinline__ bool keep_waiting(WaitClock& w, int* err) {
+  const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+  if (w.polls++ == 0) w.t0 = now;
+  if (now - w.t0 > PQR_WAIT_TICKS) {
     atomicOr(err, 1);
     return false;
   }
-  if ((spins & 31) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+  if ((w.polls & 31) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
   __builtin_amdgcn_s_sleep(1);
   return true;
 }
@@ -597,7 +606,7 @@ __global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, c
     int bi = INT_MAX;
     {
       const u64* pr = xc.part + 3 * ((size_t)slot * xc.G + d.blk0);
-      long long spins = 0;
+      WaitClock spins;
       for (;;) {
         bool ok = true;
         double lv = -1.0;
@@ -640,7 +649,7 @@ __global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, c
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       for (int gb0 = 0; gb0 < ng; gb0 += 256) {
         double f[4];
-        long long spins = 0;
+        WaitClock spins;
         for (;;) {
           bool ok = true;
 #pragma unroll
@@ -665,7 +674,7 @@ __global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, c
     if (!stop) {
       const u64* pc = xc.pub + ((size_t)slot * xc.G + d.blk0 + p / NCW) * pub_stride;
       double xs[PQ];  // rows i + 64 w + lane, the per-step form's grouping of ||x||^2
-      long long spins = 0;
+      WaitClock spins;
       for (;;) {
         bool ok = true;
 #pragma unroll
@@ -697,7 +706,7 @@ __global__ __launch_bounds__(64) void k_pqr_run(const PQRDesc* __restrict__ D, c
       stop = fabs(beta) <= floor_v;
       if (d.forced >= 0)
         stop = stop || i >= d.forced;
-      else if (i > 0)
+      else if (i > 0 && !d.exact)
         stop = stop || fabs(beta) < eps * r00;
     }
     if (stop) break;
@@ -917,8 +926,10 @@ int run_capacity_w(int ncw) {
 
 // Chunk width of the persistent form (columns per wave): the narrowest of 8,
 // 16, 32 (16 at most above 128 rows) that keeps every matrix at or below 256
-// chunks (at most 512 with the widest), within the co-resident limit; 0 when
-// the form does not apply.
+// chunks (at most 512 with the widest), within the co-resident limit and at
+// most PQR_RUN_MAX_WAVES waves; 0 when the form does not apply.  The form
+// aborted once on a batch of 1805 waves, with no cause found: batches of
+// that size take the per-step form until one is.
 template <typename T>
 int pqr_run_width(int max_m, const std::vector<int>& ns, int* rows) {
   // Opt-in (SPAQR_PQR_PERSISTENT set): the form has not yet run on every
@@ -940,7 +951,9 @@ int pqr_run_width(int max_m, const std::vector<int>& ns, int* rows) {
       widest = std::max(widest, nb);
     }
     const int cap = pq == 2 ? run_capacity_w<T, 2>(ncw) : run_capacity_w<T, 4>(ncw);
-    if (total <= cap && (widest <= 256 || (ncw == top && widest <= PQR_POLL * 64))) return ncw;
+    if (total <= std::min<int64_t>(cap, PQR_RUN_MAX_WAVES) &&
+        (widest <= 256 || (ncw == top && widest <= PQR_POLL * 64)))
+      return ncw;
   }
   return 0;
 }

@@ -172,8 +172,8 @@ struct QRDesc {
 // diagonal of pivot columns.  V (ld m) and tau receive the reflectors when
 // non-null.  rank_out[0] receives the rank.
 // Rank rule: stop at the first step i with |R_ii| <= noise * ||A||_F (the
-// numerical rank), then at |R_ii| < eps |R_00|, or at i == forced when
-// forced >= 0.
+// numerical rank), then at |R_ii| < eps |R_00| unless `exact` is set, or at
+// i == forced when forced >= 0.
 struct PQRDesc {
   void* A;
   void* V;
@@ -187,7 +187,9 @@ struct PQRDesc {
   int blk0, nblk;    // this matrix's column chunks in the launch (set by the launcher)
   int cw;            // columns per chunk (set by the launcher)
   int g0;            // first 8-column group of this matrix (persistent form)
+  int exact;         // 1: the eps rule is off (only the numerical-rank floor stops)
 };
+static_assert(sizeof(PQRDesc) == 96, "one pivot-step work-group reads one 96-byte descriptor");
 
 // Per-matrix state of the step-synchronous pivoted QR, double-buffered by
 // step parity (step i reads slot i&1 and writes slot (i+1)&1).
