@@ -144,6 +144,19 @@ int spaqr_factorize_forced(spaqr_handle h, double eps, const int32_t* ranks, int
  * b_dev: M doubles; x_dev: N doubles, original column order. */
 int spaqr_apply(spaqr_handle h, const double* b_dev, double* x_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as spaqr_apply, bit for bit, with every intermediate in the
+ * library's static device scratch array of 2^21 doubles (16 MiB, held by
+ * each GPU the library runs on until the process ends) instead of handle
+ * or freshly allocated memory.  The call allocates nothing; it needs
+ * N + (W-sweep staging) + (W-sweep partials) doubles, each part rounded up
+ * to 256 bytes, and returns SPAQR_EARG (naming the size) above the limit.
+ * All calls on one GPU share the array: calls that overlap on one GPU
+ * (other streams or threads) race.  SPAQR_ESTATE before a factorization.
+ * b_dev: M doubles; x_dev: N doubles, original column order. */
+int spaqr_apply_noalloc(spaqr_handle h, const double* b_dev, double* x_dev);
+
 /* out = W^-1 in or W^-T in, both N doubles in slot space (Section 2.7). */
 int spaqr_apply_op(spaqr_handle h, int32_t op, const double* in_dev, double* out_dev);
 

@@ -109,6 +109,14 @@ int spaqr_apply(spaqr_handle h, const double* b_dev, double* x_dev) {
   });
 }
 
+int spaqr_apply_noalloc(spaqr_handle h, const double* b_dev, double* x_dev) {
+  return guard(h, [&]() -> int {
+    if (!h || !b_dev || !x_dev) throw spaqr::Error(SPAQR_EARG, "null argument");
+    spaqr::csne_noalloc(h->h, b_dev, x_dev);
+    return SPAQR_OK;
+  });
+}
+
 int spaqr_apply_op(spaqr_handle h, int32_t op, const double* in_dev, double* out_dev) {
   return guard(h, [&]() -> int {
     if (!h || !in_dev || !out_dev) throw spaqr::Error(SPAQR_EARG, "null argument");

@@ -1508,6 +1508,8 @@ void Factorizer<T>::build_apply() {
   }
   H.d_nstage = max_stage > 0 ? static_cast<double*>(H.arena.alloc(max_stage * sizeof(double))) : nullptr;
   H.d_awork = max_work > 0 ? static_cast<double*>(H.arena.alloc(max_work * sizeof(double))) : nullptr;
+  H.nstage_elems = max_stage;
+  H.awork_elems = max_work;
 }
 
 template <typename T>
@@ -1627,31 +1629,33 @@ void factorize(Handle& H, double eps, const int* forced, int nforced) {
   H.factored = true;
 }
 
-void apply_op(Handle& H, bool transpose, double* x) {
+void apply_op(Handle& H, bool transpose, double* x, double* stage, double* work, bool timing) {
+  if (!stage) stage = H.d_nstage;
+  if (!work) work = H.d_awork;
   const int nb = (int)H.batches.size();
   for (int k = 0; k < nb; ++k) {
     const ApplyBatch& b = H.batches[transpose ? k : nb - 1 - k];
-    const bool timed = H.kt.pick("apply");
+    const bool timed = timing && H.kt.pick("apply");
     if (timed) H.kt.mark(H.stream);
     const bool f32 = H.precision == SPAQR_FP32_FACTOR;
     if (!transpose && b.nchunks > 0) {
       if (f32)
-        launch_apply_gemv<float>(b.d_ops, b.d_chunks, b.nchunks, false, x, H.d_nstage, H.d_awork, H.stream);
+        launch_apply_gemv<float>(b.d_ops, b.d_chunks, b.nchunks, false, x, stage, work, H.stream);
       else
-        launch_apply_gemv<double>(b.d_ops, b.d_chunks, b.nchunks, false, x, H.d_nstage, H.d_awork, H.stream);
+        launch_apply_gemv<double>(b.d_ops, b.d_chunks, b.nchunks, false, x, stage, work, H.stream);
     }
     if (f32)
-      launch_apply_batch<float>(b.d_ops, b.n, b.max_n1, transpose, x, H.d_nstage, H.d_awork, H.stream);
+      launch_apply_batch<float>(b.d_ops, b.n, b.max_n1, transpose, x, stage, work, H.stream);
     else
-      launch_apply_batch<double>(b.d_ops, b.n, b.max_n1, transpose, x, H.d_nstage, H.d_awork, H.stream);
+      launch_apply_batch<double>(b.d_ops, b.n, b.max_n1, transpose, x, stage, work, H.stream);
     if (transpose && b.nchunks > 0) {
       if (f32)
-        launch_apply_gemv<float>(b.d_ops, b.d_chunks, b.nchunks, true, x, H.d_nstage, H.d_awork, H.stream);
+        launch_apply_gemv<float>(b.d_ops, b.d_chunks, b.nchunks, true, x, stage, work, H.stream);
       else
-        launch_apply_gemv<double>(b.d_ops, b.d_chunks, b.nchunks, true, x, H.d_nstage, H.d_awork, H.stream);
+        launch_apply_gemv<double>(b.d_ops, b.d_chunks, b.nchunks, true, x, stage, work, H.stream);
     }
     if (transpose && b.n_nslots > 0)
-      launch_apply_nsum(b.d_nslots, b.d_nptr, b.d_noff, b.n_nslots, H.d_nstage, x, H.stream);
+      launch_apply_nsum(b.d_nslots, b.d_nptr, b.d_noff, b.n_nslots, stage, x, H.stream);
     if (timed) {
       H.kt.mark(H.stream);
       H.kt.bytes += b.bytes;

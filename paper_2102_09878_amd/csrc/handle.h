@@ -182,6 +182,8 @@ struct Handle {
   std::vector<ApplyBatch> batches;
   double* d_nstage = nullptr;  // contributions R_sN^T x_s of one batch (arena)
   double* d_awork = nullptr;   // chunk partials / t vectors of one batch (arena)
+  int64_t nstage_elems = 0;    // sizes of those two (doubles)
+  int64_t awork_elems = 0;
   std::vector<int> ranks;
   spaqr_stats stats{};
   KernelTimer kt;
@@ -197,12 +199,19 @@ struct Handle {
 };
 
 void factorize(Handle& H, double eps, const int* forced, int nforced);
-void apply_op(Handle& H, bool transpose, double* x_dev);
+// W^-1 (or W^-T) applied in place to x_dev, batch by batch.  stage / work
+// default to the handle's staging buffers (d_nstage, d_awork); timing off
+// skips the per-kernel timer (which may allocate event and stamp storage).
+void apply_op(Handle& H, bool transpose, double* x_dev, double* stage = nullptr, double* work = nullptr,
+              bool timing = true);
 // CGLS on every problem of the plan at once, each with its own scalars and
 // stopping test; infos[count] (may be null).  Returns SPAQR_NOCONV if any
 // problem reached max_iter.
 int cgls(Handle& H, const double* b, double tol, int max_iter, double* x, spaqr_cgls_info* infos);
 void csne(Handle& H, const double* b, double* x);
+// The same solve with every intermediate in the library's static device
+// scratch array (no device allocation in the call).
+void csne_noalloc(Handle& H, const double* b, double* x);
 // Column scaling of the current device values d_vals: D, Ahat, Ahat^T and
 // the ||A||_2 estimate, all on the device.
 void scale_values(Handle& H);

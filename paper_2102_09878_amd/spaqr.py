@@ -21,7 +21,7 @@ FP64, FP32_FACTOR = 0, 1
 WINV, WINVT = 0, 1
 
 EXPORTS = ["spaqr_analyze", "spaqr_get_ordering", "spaqr_set_values", "spaqr_factorize",
-           "spaqr_factorize_forced", "spaqr_apply", "spaqr_apply_op", "spaqr_cgls", "spaqr_factor_stats",
+           "spaqr_factorize_forced", "spaqr_apply", "spaqr_apply_noalloc", "spaqr_apply_op", "spaqr_cgls", "spaqr_factor_stats",
            "spaqr_get_ranks", "spaqr_get_op", "spaqr_time_kernel", "spaqr_adjoint", "spaqr_batch_analyze",
            "spaqr_batch_info", "spaqr_batch_cgls", "spaqr_destroy", "spaqr_last_error"]
 
@@ -75,6 +75,7 @@ def load(path: str = LIB_PATH):
         "spaqr_factorize": [P, D],
         "spaqr_factorize_forced": [P, D, P, I32],
         "spaqr_apply": [P, P, P],
+        "spaqr_apply_noalloc": [P, P, P],
         "spaqr_apply_op": [P, I32, P, P],
         "spaqr_cgls": [P, P, D, I32, P, ctypes.POINTER(CglsInfo)],
         "spaqr_factor_stats": [P, ctypes.POINTER(Stats)],
@@ -167,6 +168,11 @@ def spaqr_factorize_forced(h, eps, ranks):
 def spaqr_apply(h, b_dev, x_dev):
     lib = load()
     _check(lib, h, lib.spaqr_apply(h, _ptr(_dev_f64(b_dev)), _ptr(_dev_f64(x_dev))))
+
+
+def spaqr_apply_noalloc(h, b_dev, x_dev):
+    lib = load()
+    _check(lib, h, lib.spaqr_apply_noalloc(h, _ptr(_dev_f64(b_dev)), _ptr(_dev_f64(x_dev))))
 
 
 def spaqr_apply_op(h, op, in_dev, out_dev):
@@ -348,6 +354,11 @@ class Solver:
         x = torch.empty(self.N, dtype=torch.float64, device=b_dev.device)
         spaqr_apply(self.h, b_dev, x)
         return x
+
+    def apply_noalloc(self, b_dev, x_dev):
+        """spaqr_apply into a caller-provided x_dev, with no device allocation."""
+        spaqr_apply_noalloc(self.h, b_dev, x_dev)
+        return x_dev
 
     def apply_op(self, op, v_dev):
         import torch

@@ -113,6 +113,8 @@ def test_call_order_errors_without_gpu_work():
     assert lib.spaqr_factor_stats(s.h, ctypes.byref(st)) == b.ESTATE
     assert lib.spaqr_apply_op(s.h, 0, dummy, dummy) == b.ESTATE
     assert lib.spaqr_apply_op(s.h, 7, dummy, dummy) == b.EARG
+    assert lib.spaqr_apply_noalloc(s.h, dummy, dummy) == b.ESTATE
+    assert lib.spaqr_apply_noalloc(s.h, None, dummy) == b.EARG
     assert lib.spaqr_factorize(s.h, -1.0) == b.EARG
     s.close()
 
