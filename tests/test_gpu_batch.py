@@ -1,13 +1,15 @@
 """GPU parity of the batching form: independent problems factorized in one
 handle (same-level fronts of all members in the same launches) and solved
-by per-member CGLS, against each member factorized alone and against the
-least-squares solution."""
+by per-member CGLS, against each member factorized alone, against the
+oracle's factor of each member (FP64) and against the least-squares
+solution."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
 
 import paper_2102_09878_amd as pk
 from oracle import adjoint as oadj
+from oracle import spaqr as osp
 from synth import batch_problem, batch_sides, grid_ls
 
 pytestmark = pytest.mark.gpu
@@ -64,6 +66,16 @@ def test_batch_members_equal_standalone(precision):
                 assert (o["nslots"] - c0 == r["nslots"]).all(), (g, i)
             scale = max(1.0, np.abs(r["mat"]).max()) if r["mat"].size else 1.0
             assert np.abs(o["mat"] - r["mat"]).max(initial=0.0) <= 1e-12 * scale, (g, i)
+        if precision == "fp64":
+            # the member's ops taken from the batch handle against the oracle
+            f = osp.factorize(osp.analyze(p, d), eps, 1)
+            assert len(f.ops) == len(mine), g
+            for i, (o, fo) in enumerate(zip(mine, f.ops)):
+                ref = fo[3] if fo[0] == "elim" else fo[2]
+                assert o["kind"] == fo[0] and np.array_equal(o["slots"] - c0, fo[1]), (g, i)
+                assert o["mat"].shape == ref.shape, (g, i)
+                if ref.size:
+                    assert np.abs(o["mat"] - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max()), (g, i)
         x, info = s.cgls(dev(p.b), tol=1e-12)
         assert infos[g]["converged"] and infos[g]["iters"] == info["iters"], (g, infos[g], info)
         assert np.abs(x_all[c0:c1] - host(x)).max() <= 1e-10 * np.abs(host(x)).max()
