@@ -10,13 +10,18 @@ HBM.  Both precision forms are measured (FP64 fronts/factors, and FP32
 fronts/factors with FP64 CGLS); the faster one is reported as `value`.
 
 Prints ONE JSON line.  `roofline` describes the dominant kernel (one pivot
-step of the batched rank-revealing QRs), timed live over the timed region
-(every --every-th launch): the timed launches stamp their own start and end
-with the GPU's constant-rate clock, so `avg_launch_us` is the kernel
-duration a profiler reports (no launch gaps).  `traffic` comes from the
-counter profile in profiles/ while the kernel source is unchanged since it
-was taken, else null.  `cpu_baseline` times the FP64 CPU oracle on a
-bounded sample.
+step of the batched rank-revealing QRs), timed live over the timed region:
+every launch stamps its own start and end with the GPU's constant-rate
+clock on the stream it runs on, so `avg_launch_us` is the kernel duration a
+profiler reports (no launch gaps).  Its algorithmic work is the pivoted-QR
+count of Section 8(d) of the design notes: per matrix m x n of rank r,
+4mnr - 2r^2(m+n) + 4r^3/3 + 2mn flops and its block read once plus its kept
+rows written once; the updates run in FP64 arithmetic (FP64 column norms
+decide the pivots and ranks), so at about 50 flop/byte the roof is the FP64
+vector rate, not HBM.  `traffic` is the counter-measured HBM traffic per
+launch from profiles/ while the kernel source is unchanged since it was
+taken, else null.  `cpu_baseline` times the FP64 CPU oracle on a bounded
+sample and extrapolates it (stated in `sample`).
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1]
 """
@@ -34,22 +39,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "factor+CGLS time to 1e-10 residual (s) at 256² grid; factor HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_TFLOPS = 78.6    # 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+FP32_TFLOPS = 157.3        # FP32 vector / MFMA dense peak
 
 
-def _counter_traffic(kernel_src: str):
-    """Measured HBM bytes per launch of the dominant kernel (FETCH_SIZE +
-    WRITE_SIZE, copy-calibrated) from profiles/, if the kernel source still
-    has the hash recorded with the counters; else None."""
+def _counters(name: str, sources):
+    """A counter record from profiles/ if every listed source still has the
+    SHA-256 recorded with the counters; else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "pmc_k_pqr_step.json")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(os.path.join(ROOT, kernel_src), "rb").read()).hexdigest()
+        for src in sources:
+            sha = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+            if rec.get("sources", {}).get(src) != sha:
+                return None
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != sha:
+    return rec
+
+
+def _golden(cfg: int):
+    """The oracle's stored full-size run (tests/golden, written from oracle/ only)."""
+    try:
+        return json.load(open(os.path.join(ROOT, "tests", "golden", f"full_size_cfg{cfg}.json")))
+    except (OSError, ValueError):
         return None
-    return rec.get("bytes_per_launch")
 
 
 def _cpu_baseline(seconds_budget: float, target_flops: float) -> dict:
@@ -77,11 +92,15 @@ print(json.dumps(dict(seconds=dt, flops=sum(v[0] for v in f.ledger.values()), it
         raise RuntimeError(out.stderr[-2000:])
     r = json.loads(out.stdout.strip().splitlines()[-1])
     rate = r["flops"] / r["seconds"]
-    return {"value": target_flops / rate, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": ("FP64 oracle (python/numpy, 1 thread), full analyze+factor+CGLS to 1e-10 on the "
-                       f"128x128 instance of the same recipe (depth 7): {r['seconds']:.1f} s for "
-                       f"{r['flops']:.3e} algorithmic flops; scaled to the {target_flops:.3e} flops of the "
-                       "256x256 job")}
+    gold = _golden(2)
+    full = (f"; the full 256x256 oracle run (analyze + factorize + CGLS) was measured once at "
+            f"{sum(gold['oracle_seconds'].values()):.0f} s on the 8-core build container with 2 BLAS threads"
+            if gold else "")
+    return {"value": target_flops / rate, "unit": "s", "cores": 1, "kind": "oracle", "extrapolated": True,
+            "sample": ("EXTRAPOLATED: FP64 oracle (python/numpy, 1 thread) timed on the host for a full "
+                       "analyze+factor+CGLS to 1e-10 on the 128x128 instance of the same recipe (depth 7): "
+                       f"{r['seconds']:.1f} s for {r['flops']:.3e} algorithmic flops, scaled to the "
+                       f"{target_flops:.3e} flops of the 256x256 job" + full)}
 
 
 def _batch_form(steps: int, warmup: int) -> dict:
@@ -127,7 +146,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--forms", default="fp32,fp64")
     ap.add_argument("--family", default="pqr_step")
-    ap.add_argument("--every", type=int, default=8)
+    ap.add_argument("--every", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch form")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -156,8 +175,10 @@ def main() -> int:
 
     cfg = CONFIGS[2]
     prob = config_problem(2)
+    gold = _golden(2)
     b = torch.as_tensor(prob.b, device="cuda")
     forms = {}
+    xs = {}
     for form in args.forms.split(","):
         s = pk.Solver.from_problem(prob, cfg["depth"], cfg["skip"], precision=form)
         for _ in range(args.warmup):
@@ -183,29 +204,68 @@ def main() -> int:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         st = s.stats()
+        kern = dict(calls=st["kernel_calls"], seconds=st["kernel_seconds"], bytes=st["kernel_bytes"],
+                    flops=st["kernel_flops"])
+        # outside the timed region: the cooperative tall-panel kernel, timed
+        # through the library's own hook (one more factorization)
+        s.time_kernel("qrp_coop", 1)
+        s.factorize(cfg["eps"])
+        sc = s.stats()
+        s.time_kernel(None, 1)
+        xh = x.cpu().numpy()
+        xs[form] = xh
         ok = all(r <= 1e-10 for r in res)
+        el_tflops = st["flops"]["eliminate"] / phase["eliminate"] / 1e12 if phase.get("eliminate") else None
+        peak = FP32_TFLOPS if form == "fp32" else FP64_VALU_TFLOPS
         forms[form] = dict(
             s_per_step=(t1 - t0) / args.steps, factor_s=f_sec / args.steps, cgls_s=c_sec / args.steps,
             cgls_iters=iters[-1], residual=max(res), converged=ok, phase_gpu_s=phase,
-            factor_gbs=fac_bytes / f_sec / 1e9 if f_sec > 0 else None,
-            factor_flops=sum(st["flops"].values()), mem_factor=st["mem_factor"],
-            kernel=dict(calls=st["kernel_calls"], seconds=st["kernel_seconds"], bytes=st["kernel_bytes"],
-                        flops=st["kernel_flops"]))
+            factor_gbs_algorithmic=fac_bytes / f_sec / 1e9 if f_sec > 0 else None,
+            factor_flops=sum(st["flops"].values()), factor_flops_by_phase=st["flops"], mem_factor=st["mem_factor"],
+            eliminate_tflops=el_tflops, eliminate_peak_tflops=peak,
+            eliminate_frac=el_tflops / peak if el_tflops else None,
+            qrp_coop=(dict(launches=sc["kernel_calls"], avg_us=sc["kernel_seconds"] / sc["kernel_calls"] * 1e6,
+                           tflops=sc["kernel_flops"] / sc["kernel_seconds"] / 1e12)
+                      if sc["kernel_calls"] else None),
+            kernel=kern)
+        if gold:
+            xi = np.asarray(gold["x_index"])
+            forms[form]["x_err_vs_oracle"] = float(np.abs(xh[xi] - np.asarray(gold["x_values"])).max() /
+                                                   gold["x_norm"])
+            forms[form]["x_err_vs_oracle_note"] = ("max over the oracle's 512 stored entries of x (CGLS to 1e-12) "
+                                                   "of |x - x_oracle|, relative to ||x_oracle||; x here stops at 1e-10")
+            forms[form]["cgls_iters_oracle"] = gold["cgls_1e10"]["iters"]
         s.close()
+    if "fp32" in xs and "fp64" in xs:
+        forms["fp32"]["x_err_vs_fp64_form"] = float(np.linalg.norm(xs["fp32"] - xs["fp64"]) /
+                                                    np.linalg.norm(xs["fp64"]))
     batch = None if args.no_batch else _batch_form(args.steps, args.warmup)
     best = min(forms, key=lambda k: forms[k]["s_per_step"] if forms[k]["converged"] else 1e30)
     bf = forms[best]
     kern = bf["kernel"]
     roofline = None
-    if kern["calls"] and kern["seconds"] > 0:
-        achieved = kern["bytes"] / kern["seconds"] / 1e9
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": _counter_traffic("paper_2102_09878_amd/csrc/pqr.hip"),
-                    "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+    if kern["calls"] and kern["seconds"] > 0 and args.family == "pqr_step":
+        per_launch = kern["bytes"] / kern["calls"]
+        tf = kern["flops"] / kern["seconds"] / 1e12
+        cnt = _counters("pmc_k_pqr_step.json", ["paper_2102_09878_amd/csrc/pqr.hip"])
+        traffic = cnt["bytes_per_launch"] if cnt else None
+        roofline = {"bound": "alu", "achieved": tf, "peak": FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tf / FP64_VALU_TFLOPS, "traffic": traffic,
+                    "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    "traffic_over_algorithmic": traffic / per_launch if traffic else None,
                     "kernel": f"k_pqr_step<{'float' if best == 'fp32' else 'double'}>",
-                    "avg_launch_us": kern["seconds"] / kern["calls"] * 1e6,
-                    "bytes_per_launch": kern["bytes"] / kern["calls"], "timed_launches": kern["calls"]}
+                    "avg_launch_us": kern["seconds"] / kern["calls"] * 1e6, "timed_launches": kern["calls"],
+                    "algorithmic_flops_per_launch": kern["flops"] / kern["calls"],
+                    "algorithmic_bytes_per_launch": per_launch,
+                    "intensity_flop_per_byte": kern["flops"] / kern["bytes"] if kern["bytes"] else None,
+                    "hbm_view": {"achieved_gbs": kern["bytes"] / kern["seconds"] / 1e9, "peak_gbs": HBM_PEAK_GBS,
+                                 "frac": kern["bytes"] / kern["seconds"] / 1e9 / HBM_PEAK_GBS},
+                    "note": ("one launch is one pivot step of every matrix of a batch; rank-revealing QRs are a "
+                             "chain of dependent steps (one global argmax per pivot), so the kernel is bound by "
+                             "the step latency, far from either roof")}
+    cnt_f = _counters(f"pmc_factor_cfg2_{best}.json", ["paper_2102_09878_amd/csrc/" + f for f in
+                                                        ("factor.hip", "qr.hip", "pqr.hip", "kernels.hip")])
+    factor_hbm_counters = cnt_f["factor_bytes"] / bf["factor_s"] / 1e9 if cnt_f else None
     cpu = None
     if not args.no_cpu_baseline:
         try:
@@ -221,8 +281,12 @@ def main() -> int:
         "config": {"workload": "grid2d_256x256 LS: Laplacian + 65536 random local rows, seed 1",
                    "M": prob.M, "N": prob.N, "nnz": prob.nnz, "nd_depth": cfg["depth"], "eps": cfg["eps"],
                    "sparsify_skip": cfg["skip"], "cgls_tol": 1e-10, "form": best},
-        "factor_hbm_gbs": bf["factor_gbs"],
+        "factor_hbm_gbs": factor_hbm_counters,
+        "factor_hbm_gbs_note": ("rocprofv3 FETCH_SIZE + WRITE_SIZE of one factorization (profiles/, copy-calibrated) "
+                                "over the factor time; null when the kernel sources changed since the counters"),
+        "factor_gbs_algorithmic": bf["factor_gbs_algorithmic"],
         "cgls_iters": bf["cgls_iters"], "final_residual": bf["residual"],
+        "x_err_vs_oracle": bf.get("x_err_vs_oracle"),
         "roofline": roofline, "cpu_baseline": cpu,
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "kernel"} for k, v in forms.items()},
         "batch_form": batch,

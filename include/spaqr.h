@@ -220,8 +220,10 @@ int spaqr_factor_stats(spaqr_handle h, spaqr_stats* out);
  * events on the handle's stream and count the algorithmic bytes and flops
  * of the timed launches (exposed through spaqr_factor_stats); resets the
  * counters.  family: "pqr_step" (one pivot step of the batched
- * rank-revealing QRs) or "apply" (one batch of W^-1 / W^-T ops), or
- * NULL / "" to stop.  SPAQR_EARG for an unknown family or every < 1.
+ * rank-revealing QRs: algorithmic flops and bytes of each batch, block read
+ * and kept rows written once, shared over its step launches), "apply" (one
+ * batch of W^-1 / W^-T ops) or "qrp_coop" (one cooperative tall Householder
+ * panel of an elimination round), or NULL / "" to stop.  SPAQR_EARG for an unknown family or every < 1.
  * Measurement aid: each timed launch adds two event records. */
 int spaqr_time_kernel(spaqr_handle h, const char* family, int32_t every);
 

@@ -233,7 +233,7 @@ int spaqr_time_kernel(spaqr_handle h, const char* family, int32_t every) {
   return guard(h, [&]() -> int {
     if (!h) throw spaqr::Error(SPAQR_EARG, "null handle");
     const std::string f = family ? family : "";
-    if (!f.empty() && f != "pqr_step" && f != "apply")
+    if (!f.empty() && f != "pqr_step" && f != "apply" && f != "qrp_coop")
       throw spaqr::Error(SPAQR_EARG, "unknown kernel family '" + f + "'");
     if (every < 1) throw spaqr::Error(SPAQR_EARG, "every must be >= 1");
     h->h.kt.reset(f.c_str(), every);

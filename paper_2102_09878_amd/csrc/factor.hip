@@ -392,24 +392,24 @@ class Factorizer {
   }
   std::vector<std::pair<double*, size_t>> qrpool_;
 
-  // Algorithmic traffic of a timed rank-revealing-QR batch, once its ranks
-  // are known: at step i a live matrix reads and writes its (m-i) x (n-i-1)
-  // trailing block and reads its pivot column.
+  // Algorithmic work of a rank-revealing-QR batch whose step launches were
+  // timed, once its ranks are known: per matrix (m x n, rank r) the flops
+  // of a pivoted QR truncated at r, 4mnr - 2r^2(m+n) + 4r^3/3 plus 2mn for
+  // the column norms, and its block read once and its kept rows written
+  // once, s (mn + rn) bytes; each timed launch (one pivot step of every
+  // matrix of the batch) is credited its share, timed / launched.
   void account_pqr(const std::vector<PQRDesc>& q, const int* ranks) {
-    if (!H.kt.on("pqr_step")) return;
-    for (int i : timed_steps_)
-      for (size_t k = 0; k < q.size(); ++k) {
-        const double m = q[k].m, n = q[k].n;
-        const int r = ranks[k];
-        if (i < r) {
-          H.kt.bytes += sizeof(T) * ((m - i) * (n - i - 1) * 2.0 + (m - i));
-          H.kt.flops += 4.0 * (m - i) * (n - i - 1);
-        } else if (i == r && r < std::min(q[k].m, q[k].n)) {
-          H.kt.bytes += sizeof(T) * (m - r);
-        }
-      }
+    if (!H.kt.on("pqr_step") || pqr_launched_ == 0) return;
+    const double share = (double)timed_steps_.size() / pqr_launched_;
+    for (size_t k = 0; k < q.size(); ++k) {
+      const double m = q[k].m, n = q[k].n, r = ranks[k];
+      H.kt.flops += share * (4 * m * n * r - 2 * r * r * (m + n) + 4 * r * r * r / 3 + 2 * m * n);
+      H.kt.bytes += share * sizeof(T) * (m * n + r * n);
+    }
     timed_steps_.clear();
+    pqr_launched_ = 0;
   }
+  int pqr_launched_ = 0;
   std::vector<int> timed_steps_;
 
   // After a sync: a persistent pivoted QR that abandoned a wait left ranks of
@@ -424,7 +424,7 @@ class Factorizer {
     if (pqr_err_h_ && *pqr_err_h_) {
       *pqr_err_h_ = 0;
       SPAQR_HIP(hipMemset(H.d_pqr_err, 0, sizeof(int)));
-      throw Error(SPAQR_EHIP, "pivoted QR: a work-group exchange wait exceeded its limit");
+      throw Error(SPAQR_EHIP, "a wait between the work-groups of a kernel exceeded its time limit");
     }
   }
 
@@ -531,7 +531,9 @@ class Factorizer {
     ++launches_;
     int steps = 0;
     timed_steps_.clear();
+    pqr_launched_ = 0;
     while (steps < kmax) {
+      ++pqr_launched_;
       const bool timed = H.kt.pick("pqr_step");
       unsigned long long* stamp = timed ? H.kt.stamp(st) : nullptr;
       if (timed) timed_steps_.push_back(steps);
@@ -572,7 +574,7 @@ class Factorizer {
     ws.gp = scratch(qrpool_, 4, nf * ws.MS * QR_NB * QR_NB);
     ws.wp = scratch(qrpool_, 5, nf * ws.MT * ws.MS * QR_NB * QR_TN);
     ws.w = scratch(qrpool_, 6, nf * ws.MT * QR_NB * QR_TN);
-    launch_qr<T>(d, q, ws, st, &launches_);
+    launch_qr<T>(d, q, ws, st, &launches_, &H.kt);
   }
 
   int* flags_ = nullptr;

@@ -22,6 +22,7 @@
 
 #include <cstdlib>
 
+#include "handle.h"
 #include "spaqr_impl.h"
 #include "wave.h"
 
@@ -998,7 +999,7 @@ void qr_work_dims(const std::vector<QRDesc>& h, int* MS, int* MT) {
 
 template <typename T>
 void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork& ws, hipStream_t s,
-               int* launches) {
+               int* launches, KernelTimer* kt) {
   if (h.empty()) return;
   const unsigned nf = (unsigned)h.size();
   int kmax = 0, mmax = 0;
@@ -1040,7 +1041,21 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork&
       int a_j0 = j0, a_kb = kbmax, a_s = coop_segs;
       QRWork a_ws = ws;
       void* args[] = {(void*)&dd, (void*)&a_j0, (void*)&a_kb, (void*)&a_s, (void*)&a_ws};
+      const bool timed = kt && kt->pick("qrp_coop");
+      if (timed) kt->mark(s);
       SPAQR_HIP(hipLaunchCooperativeKernel((const void*)k_qrp_coop, dim3(nf * coop_segs), dim3(PBS), args, 0, s));
+      if (timed) {
+        kt->mark(s);
+        // algorithmic work of the panel: Householder QR of (m - j0) x kb,
+        // the panel read and written once
+        for (auto& d : h) {
+          const int kk = std::min(d.m, d.k);
+          if (j0 >= kk) continue;
+          const double mr = d.m - j0, kb = std::min(NB, kk - j0);
+          kt->flops += 2.0 * mr * kb * kb - 2.0 * kb * kb * kb / 3.0;
+          kt->bytes += 2.0 * sizeof(T) * mr * kb;
+        }
+      }
       ++*launches;
     } else if (split) {
       const dim3 g(nf, segs);
@@ -1080,7 +1095,9 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork&
   }
 }
 
-template void launch_qr<double>(const QRDesc*, const std::vector<QRDesc>&, const QRWork&, hipStream_t, int*);
-template void launch_qr<float>(const QRDesc*, const std::vector<QRDesc>&, const QRWork&, hipStream_t, int*);
+template void launch_qr<double>(const QRDesc*, const std::vector<QRDesc>&, const QRWork&, hipStream_t, int*,
+                                KernelTimer*);
+template void launch_qr<float>(const QRDesc*, const std::vector<QRDesc>&, const QRWork&, hipStream_t, int*,
+                               KernelTimer*);
 
 }  // namespace spaqr

@@ -13,6 +13,7 @@
 #include "../../include/spaqr.h"
 
 namespace spaqr {
+struct KernelTimer;
 
 struct Error : std::runtime_error {
   int code;
@@ -311,8 +312,10 @@ struct QRWork {
 };
 void qr_work_dims(const std::vector<QRDesc>& h, int* MS, int* MT);
 template <typename T>
+// kt (may be null): the handle's kernel timer; family "qrp_coop" brackets
+// every cooperative tall-panel launch with events.
 void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h_desc, const QRWork& ws, hipStream_t s,
-               int* launches);
+               int* launches, KernelTimer* kt);
 // Column-pivoted QR of a batch, one launch per pivot step (columns split in
 // chunks of PQR_CW over work-groups).  The caller provides device scratch:
 // states (2 per matrix), parts (2 per chunk), frop (squared Frobenius norm
