@@ -144,6 +144,17 @@ int spaqr_factorize_forced(spaqr_handle h, double eps, const int32_t* ranks, int
  * b_dev: M doubles; x_dev: N doubles, original column order. */
 int spaqr_apply(spaqr_handle h, const double* b_dev, double* x_dev);
 
+/* Corrected seminormal equations with iterative refinement (Section 1:
+ * the solution from W^T W x = A^T b, refined): x_0 = D^-1 W^-1 W^-T D^-1
+ * A^T b, then x += D^-1 W^-1 W^-T D^-1 A^T (b - A x) until
+ * ||A^T (b - A x)|| <= tol ||A||_2 ||b|| (checked before every
+ * correction) or max_steps corrections were made.  b_dev: M doubles,
+ * x_dev: N doubles (original order); info (may be NULL) gets the number of
+ * corrections in iters and the final residuals (the worst problem of a
+ * batch handle).  SPAQR_NOCONV when tol was not reached (x is written). */
+int spaqr_csne(spaqr_handle h, const double* b_dev, double tol, int32_t max_steps, double* x_dev,
+               spaqr_cgls_info* info);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * solve as spaqr_apply, bit for bit, with every intermediate in the

@@ -109,6 +109,23 @@ int spaqr_apply(spaqr_handle h, const double* b_dev, double* x_dev) {
   });
 }
 
+int spaqr_csne(spaqr_handle h, const double* b_dev, double tol, int32_t max_steps, double* x_dev,
+               spaqr_cgls_info* info) {
+  return guard(h, [&]() -> int {
+    if (!h || !b_dev || !x_dev) throw spaqr::Error(SPAQR_EARG, "null argument");
+    std::vector<spaqr_cgls_info> all(h->h.P.count);
+    const int rc = spaqr::csne_refine(h->h, b_dev, tol, max_steps, x_dev, all.data());
+    if (info) {
+      // a batch reports its worst problem
+      spaqr_cgls_info w = all[0];
+      for (const auto& i : all)
+        if (i.residual > w.residual) w = i;
+      *info = w;
+    }
+    return rc;
+  });
+}
+
 int spaqr_apply_noalloc(spaqr_handle h, const double* b_dev, double* x_dev) {
   return guard(h, [&]() -> int {
     if (!h || !b_dev || !x_dev) throw spaqr::Error(SPAQR_EARG, "null argument");

@@ -39,6 +39,7 @@ void launch_normalize(double* d, const double* src, const Segs& sg, const double
 void launch_copy(double* d, const double* src, int64_t n, hipStream_t s);
 void launch_scale(double* d, const double* src, const double* w, int64_t n, bool mul, hipStream_t s);
 void launch_sub(double* d, const double* a, const double* src, int64_t n, hipStream_t s);
+void launch_add(double* d, const double* a, const double* src, int64_t n, hipStream_t s);
 void launch_fill(double* d, double v, int64_t n, hipStream_t s);
 
 // adjoint.hip

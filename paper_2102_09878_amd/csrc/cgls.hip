@@ -104,6 +104,12 @@ __global__ void k_sub(double* __restrict__ d, const double* __restrict__ a, cons
   if (i < n) d[i] = a[i] - s[i];
 }
 
+__global__ void k_add(double* __restrict__ d, const double* __restrict__ a, const double* __restrict__ s,
+                      int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) d[i] = a[i] + s[i];
+}
+
 __global__ void k_fill(double* __restrict__ d, double v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i < n) d[i] = v;
@@ -163,6 +169,12 @@ void launch_scale(double* d, const double* src, const double* w, int64_t n, bool
 void launch_sub(double* d, const double* a, const double* src, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_sub, dim3(nb(n)), dim3(BS), 0, s, d, a, src, n);
+  SPAQR_HIP(hipGetLastError());
+}
+
+void launch_add(double* d, const double* a, const double* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_add, dim3(nb(n)), dim3(BS), 0, s, d, a, src, n);
   SPAQR_HIP(hipGetLastError());
 }
 

@@ -209,6 +209,9 @@ void apply_op(Handle& H, bool transpose, double* x_dev, double* stage = nullptr,
 // problem reached max_iter.
 int cgls(Handle& H, const double* b, double tol, int max_iter, double* x, spaqr_cgls_info* infos);
 void csne(Handle& H, const double* b, double* x);
+// Corrected seminormal equations with iterative refinement (Section 1);
+// infos[count] (may be null).  SPAQR_NOCONV if a problem missed tol.
+int csne_refine(Handle& H, const double* b, double tol, int max_steps, double* x, spaqr_cgls_info* infos);
 // The same solve with every intermediate in the library's static device
 // scratch array (no device allocation in the call).
 void csne_noalloc(Handle& H, const double* b, double* x);

@@ -21,7 +21,7 @@ FP64, FP32_FACTOR = 0, 1
 WINV, WINVT = 0, 1
 
 EXPORTS = ["spaqr_analyze", "spaqr_get_ordering", "spaqr_set_values", "spaqr_factorize",
-           "spaqr_factorize_forced", "spaqr_apply", "spaqr_apply_noalloc", "spaqr_apply_op", "spaqr_cgls", "spaqr_factor_stats",
+           "spaqr_factorize_forced", "spaqr_apply", "spaqr_apply_noalloc", "spaqr_csne", "spaqr_apply_op", "spaqr_cgls", "spaqr_factor_stats",
            "spaqr_get_ranks", "spaqr_get_op", "spaqr_time_kernel", "spaqr_adjoint", "spaqr_batch_analyze",
            "spaqr_batch_info", "spaqr_batch_cgls", "spaqr_destroy", "spaqr_last_error"]
 
@@ -76,6 +76,7 @@ def load(path: str = LIB_PATH):
         "spaqr_factorize_forced": [P, D, P, I32],
         "spaqr_apply": [P, P, P],
         "spaqr_apply_noalloc": [P, P, P],
+        "spaqr_csne": [P, P, D, I32, P, ctypes.POINTER(CglsInfo)],
         "spaqr_apply_op": [P, I32, P, P],
         "spaqr_cgls": [P, P, D, I32, P, ctypes.POINTER(CglsInfo)],
         "spaqr_factor_stats": [P, ctypes.POINTER(Stats)],
@@ -187,6 +188,16 @@ def spaqr_cgls(h, b_dev, x_dev, tol=1e-10, max_iter=200):
                         ctypes.byref(info))
     _check(lib, h, rc, allow=(OK, NOCONV))
     return dict(iters=info.iters, converged=bool(info.converged), residual=info.residual,
+                paper_residual=info.paper_residual, norm_a=info.norm_a, seconds=info.seconds)
+
+
+def spaqr_csne(h, b_dev, x_dev, tol=1e-10, max_steps=50):
+    lib = load()
+    info = CglsInfo()
+    rc = lib.spaqr_csne(h, _ptr(_dev_f64(b_dev)), float(tol), int(max_steps), _ptr(_dev_f64(x_dev)),
+                        ctypes.byref(info))
+    _check(lib, h, rc, allow=(OK, NOCONV))
+    return dict(steps=info.iters, converged=bool(info.converged), residual=info.residual,
                 paper_residual=info.paper_residual, norm_a=info.norm_a, seconds=info.seconds)
 
 
@@ -337,6 +348,13 @@ class Solver:
         import torch
         x = torch.empty(self.N, dtype=torch.float64, device=b_dev.device)
         info = spaqr_cgls(self.h, b_dev, x, tol, max_iter)
+        return x, info
+
+    def csne(self, b_dev, tol=1e-10, max_steps=50):
+        """Corrected seminormal equations with iterative refinement."""
+        import torch
+        x = torch.empty(self.N, dtype=torch.float64, device=b_dev.device)
+        info = spaqr_csne(self.h, b_dev, x, tol, max_steps)
         return x, info
 
     def adjoint(self, x_dev, b_dev, g_dev, tol=1e-12, max_iter=500):
