@@ -1,1 +1,1 @@
-from .grid_ls import GridProblem, grid_ls, config_problem, batch_problem, batch_sides, default_depth, CONFIGS  # noqa: F401
+from .grid_ls import GridProblem, grid_ls, grid_square, config_problem, batch_problem, batch_sides, default_depth, CONFIGS  # noqa: F401

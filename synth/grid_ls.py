@@ -142,6 +142,36 @@ def grid_ls(grid, extra_rows: int, seed: int, with_target: bool = False) -> Grid
                        vals=vals, b=b, x_t=x_t, seed=seed)
 
 
+def grid_square(grid, seed: int, skew: float = 0.3) -> GridProblem:
+    """Square nonsymmetric grid system (M = N): the Laplacian's stencil
+    pattern with off-diagonal values -1 + skew * N(0,1), drawn independently
+    for (i, j) and (j, i), and each diagonal equal to the sum of the
+    magnitudes of its row's off-diagonals plus one per out-of-grid neighbour
+    (weakly diagonally dominant, strictly on rows next to the Dirichlet
+    boundary, irreducible: nonsingular);
+    b standard normal.  Draw order: off-diagonal values, b."""
+    if len(grid) == 2:
+        grid = (int(grid[0]), int(grid[1]), 1)
+    nx, ny, nz = (int(g) for g in grid)
+    N = nx * ny * nz
+    rng = np.random.default_rng(seed)
+    lr, lc, lv = _laplacian(nx, ny, nz)
+    order = np.lexsort((lc, lr))
+    lr, lc = lr[order], lc[order]
+    off = lr != lc
+    vals = np.zeros(lr.shape[0])
+    vals[off] = -1.0 + skew * rng.standard_normal(int(off.sum()))
+    rowsum = np.bincount(lr, weights=np.abs(vals), minlength=N)
+    nbrs = np.bincount(lr[off], minlength=N)
+    # missing (out-of-grid) neighbours count 1 each, as in the Dirichlet Laplacian
+    vals[~off] = rowsum[lr[~off]] + (6 if nz > 1 else 4) - nbrs[lr[~off]]
+    b = rng.standard_normal(N)
+    row_ptr = np.zeros(N + 1, dtype=np.int64)
+    row_ptr[1:] = np.cumsum(np.bincount(lr, minlength=N))
+    return GridProblem(grid=(nx, ny, nz), M=N, N=N, row_ptr=row_ptr, col_idx=lc.astype(np.int32),
+                       vals=vals, b=b, seed=seed)
+
+
 def default_depth(N: int) -> int:
     """Tree levels ceil(log2(N/64)) (Section 4), at least 2."""
     return max(2, int(math.ceil(math.log2(N / 64.0))))
