@@ -173,6 +173,47 @@ def _square_form(steps: int, warmup: int) -> dict:
             "rel_residual_Ax_b": rel}
 
 
+def _inverse_poisson_form(steps: int, warmup: int) -> list:
+    """The paper's own workload family (Appendices A and B): transposed
+    Jacobians of the inverse Poisson problem on a 256 x 256 grid at aspect
+    ratios about 2, 1.5 and 1.05 (eps 1e-2, 1e-2, 1e-4 as in the paper's
+    runs) and a 32^3 grid at about 1.5 (eps 1e-2); depth ceil(log2(N/64)),
+    two leaf-side levels unsparsified, FP32 factor; factorize + CGLS to
+    1e-10 per step.  The paper's iteration counts at these sizes (1e-12
+    stopping rule, other (u, z) values) are context only."""
+    import torch
+
+    import paper_2102_09878_amd as pk
+    from synth import default_depth, inverse_poisson
+
+    out = []
+    paper_iters = {(2, 2.0): 8, (2, 1.5): 10, (2, 1.05): 4, (3, 1.5): 8}
+    for n, dim, alpha, eps in ((256, 2, 2.0, 1e-2), (256, 2, 1.5, 1e-2), (256, 2, 1.05, 1e-4), (32, 3, 1.5, 1e-2)):
+        p = inverse_poisson(n, dim, alpha, seed=1)
+        depth = default_depth(p.N)
+        s = pk.Solver.from_problem(p, depth, 2, precision="fp32")
+        b = torch.as_tensor(p.b, device="cuda")
+        for _ in range(warmup):
+            s.factorize(eps)
+            s.cgls(b, tol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fs = 0.0
+        for _ in range(steps):
+            s.factorize(eps)
+            fs += s.stats()["factor_seconds"]
+            x, info = s.cgls(b, tol=1e-10)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        s.close()
+        out.append({"workload": f"inverse Poisson {dim}D n={n} alpha={p.M / p.N:.3f} (M={p.M}, N={p.N}), "
+                                f"depth {depth}, eps {eps}, seed 1",
+                    "s_per_step": dt, "factor_s": fs / steps, "cgls_iters": info["iters"],
+                    "residual": info["residual"], "converged": info["converged"],
+                    "paper_cgls_iters_context": paper_iters[(dim, alpha)]})
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,6 +328,7 @@ def main() -> int:
                                                     np.linalg.norm(xs["fp64"]))
     batch = None if args.no_batch else _batch_form(args.steps, args.warmup)
     square = None if args.no_batch else _square_form(args.steps, args.warmup)
+    invpoi = None if args.no_batch else _inverse_poisson_form(args.steps, args.warmup)
     best = min(forms, key=lambda k: forms[k]["s_per_step"] if forms[k]["converged"] else 1e30)
     bf = forms[best]
     kern = bf["kernel"]
@@ -338,6 +380,7 @@ def main() -> int:
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "kernel"} for k, v in forms.items()},
         "batch_form": batch,
         "square_form": square,
+        "inverse_poisson_form": invpoi,
     }
     print(json.dumps(line))
     return 0
