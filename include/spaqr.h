@@ -46,6 +46,8 @@ extern "C" {
 #define SPAQR_FP32_FACTOR 1   /* fronts and factors in FP32; rank decisions,  */
                               /* apply accumulation and CGLS in FP64          */
 
+#define SPAQR_MAX_LEVELS 32  /* tree levels the per-level statistics hold */
+
 #define SPAQR_WINV 0   /* out = W^-1 in  (slot space)  */
 #define SPAQR_WINVT 1  /* out = W^-T in  (slot space)  */
 
@@ -92,6 +94,15 @@ typedef struct {
   double kernel_seconds;     /* sum of their HIP-event durations                    */
   double kernel_bytes;       /* algorithmic bytes those launches move               */
   double kernel_flops;       /* algorithmic flops of those launches                 */
+  /* Per tree level m (index m, 1 <= m <= levels; index 0 unused), the
+   * quantities of Section 4.2's profiling, for sparsified levels only
+   * (zeros elsewhere): */
+  int32_t level_interfaces[SPAQR_MAX_LEVELS]; /* interfaces scaled at level m          */
+  double level_aspect[SPAQR_MAX_LEVELS];      /* median rows / columns of their        */
+                                              /* diagonal blocks at scaling            */
+  int64_t level_cols[SPAQR_MAX_LEVELS];       /* their columns before sparsification   */
+  int64_t level_rank1[SPAQR_MAX_LEVELS];      /* sum of step-1 ranks (rows kept)       */
+  int64_t level_rank2[SPAQR_MAX_LEVELS];      /* sum of step-2 ranks (columns kept)    */
 } spaqr_stats;
 
 typedef struct {

@@ -934,6 +934,7 @@ void Factorizer<T>::scale_all() {
     std::vector<int> nb, cols;
   };
   std::vector<SF> sf;
+  std::vector<double> aspects;
   for (size_t i = 0; i < ifaces.size(); ++i) {
     SF f;
     f.p = ifaces[i];
@@ -986,6 +987,11 @@ void Factorizer<T>::scale_all() {
     e.ldr = f.cs;
     e.c = f.cs;
     ed.push_back(e);
+    aspects.push_back((double)f.m / f.cs);
+    if (level_ > 0 && level_ < SPAQR_MAX_LEVELS) {
+      H.stats.level_interfaces[level_] += 1;
+      H.stats.level_cols[level_] += f.cs;
+    }
     flops_[PH_SCALE] += qr_flops(f.m, f.cs) + 4.0 * f.m * f.cs * (f.n - f.cs) - 2.0 * f.cs * f.cs * (f.n - f.cs);
     bytes_[PH_SCALE] += 2.0 * sizeof(T) * f.m * f.n;
     sf.push_back(std::move(f));
@@ -1060,6 +1066,12 @@ void Factorizer<T>::scale_all() {
   launch_trsm<T>(upload(td), (int)td.size(), td_rows, td_c, upload(trb), (int)trb.size(), st);
   ++launches_;
   timer_end();
+  // median aspect ratio of the scaled diagonal blocks (Section 4.2)
+  if (!aspects.empty() && level_ > 0 && level_ < SPAQR_MAX_LEVELS) {
+    std::sort(aspects.begin(), aspects.end());
+    const size_t k = aspects.size();
+    H.stats.level_aspect[level_] = k % 2 ? aspects[k / 2] : 0.5 * (aspects[k / 2 - 1] + aspects[k / 2]);
+  }
   // rank-deficiency flags are read together with the step-1 ranks
   flags_ = d_flags;
   nflags_ = (int)ifaces.size();
@@ -1105,6 +1117,7 @@ void Factorizer<T>::step1_all() {
     const int r = h[i];
     RG& gr = G[who[i]];
     H.ranks.push_back(r);
+    if (level_ > 0 && level_ < SPAQR_MAX_LEVELS) H.stats.level_rank1[level_] += r;
     const double m = gr.nrows, n = (double)gr.slots.size();
     flops_[PH_SPARSIFY] += 4 * m * n * r - 2.0 * r * r * (m + n) + 4.0 * r * r * r / 3 + 2 * m * n;
     bytes_[PH_SPARSIFY] += sizeof(T) * (2 * m * n);
@@ -1263,6 +1276,7 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
     S2& s = ss[i];
     const int r = h[i];
     H.ranks.push_back(r);
+    if (level_ > 0 && level_ < SPAQR_MAX_LEVELS) H.stats.level_rank2[level_] += r;
     const double m = s.cp, n = s.K;
     flops_[PH_SPARSIFY] += 4 * m * n * r - 2.0 * r * r * (m + n) + 4.0 * r * r * r / 3 + 2 * m * n;
     bytes_[PH_SPARSIFY] += sizeof(T) * (2 * m * n);

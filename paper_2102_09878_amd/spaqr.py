@@ -19,6 +19,7 @@ OK, NOCONV = 0, 1
 EARG, ESTATE, ERANK, EHIP, ENOMEM = -1, -2, -3, -4, -5
 FP64, FP32_FACTOR = 0, 1
 WINV, WINVT = 0, 1
+MAX_LEVELS = 32
 
 EXPORTS = ["spaqr_analyze", "spaqr_get_ordering", "spaqr_set_values", "spaqr_factorize",
            "spaqr_factorize_forced", "spaqr_apply", "spaqr_apply_noalloc", "spaqr_csne", "spaqr_apply_op", "spaqr_cgls", "spaqr_factor_stats",
@@ -46,7 +47,10 @@ class Stats(ctypes.Structure):
                 ("bytes", ctypes.c_double * 5), ("phase_seconds", ctypes.c_double * 5),
                 ("factor_seconds", ctypes.c_double), ("kernel_calls", ctypes.c_int64),
                 ("kernel_seconds", ctypes.c_double), ("kernel_bytes", ctypes.c_double),
-                ("kernel_flops", ctypes.c_double)]
+                ("kernel_flops", ctypes.c_double),
+                ("level_interfaces", ctypes.c_int32 * MAX_LEVELS), ("level_aspect", ctypes.c_double * MAX_LEVELS),
+                ("level_cols", ctypes.c_int64 * MAX_LEVELS), ("level_rank1", ctypes.c_int64 * MAX_LEVELS),
+                ("level_rank2", ctypes.c_int64 * MAX_LEVELS)]
 
 
 class OpDesc(ctypes.Structure):
@@ -271,7 +275,10 @@ def spaqr_factor_stats(h):
                 device_bytes=s.device_bytes, flops=dict(zip(PHASES, s.flops)),
                 bytes=dict(zip(PHASES, s.bytes)), phase_seconds=dict(zip(PHASES, s.phase_seconds)),
                 factor_seconds=s.factor_seconds, kernel_calls=s.kernel_calls,
-                kernel_seconds=s.kernel_seconds, kernel_bytes=s.kernel_bytes, kernel_flops=s.kernel_flops)
+                kernel_seconds=s.kernel_seconds, kernel_bytes=s.kernel_bytes, kernel_flops=s.kernel_flops,
+                levels_sparsified={m: dict(interfaces=s.level_interfaces[m], aspect=s.level_aspect[m],
+                                           cols=s.level_cols[m], rank1=s.level_rank1[m], rank2=s.level_rank2[m])
+                                   for m in range(1, min(MAX_LEVELS, s.levels + 1)) if s.level_interfaces[m]})
 
 
 def spaqr_get_ranks(h):

@@ -254,3 +254,23 @@ def test_config2_full_size(precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_config3_full_size(precision):
     _check_full(3, precision)
+
+
+@pytest.mark.parametrize("grid,depth,skip,eps", [((32, 32), 4, 1, 1e-2), ((48, 40), 5, 2, 1e-3)])
+def test_per_level_statistics_match_oracle(grid, depth, skip, eps):
+    """Section 4.2's per-level quantities reported by spaqr_factor_stats:
+    median aspect ratio of the scaled diagonal blocks and the step-1 and
+    step-2 ranks, equal to the oracle's (integers and ratios of integers)."""
+    p = grid_ls(grid, grid[0] * grid[1], 31)
+    an, f = _oracle(p, depth, eps, skip)
+    s = pk.Solver.from_problem(p, depth, skip)
+    s.factorize(eps)
+    lv = s.stats()["levels_sparsified"]
+    asp = dict(f.stats["aspect"])
+    r1 = {m: sum(r) for m, r in f.stats["ranks_step1"]}
+    r2 = {m: sum(r) for m, r in f.stats["ranks_step2"]}
+    assert sorted(lv) == sorted(asp) and lv
+    for m, e in lv.items():
+        assert e["aspect"] == asp[m], m
+        assert e["rank1"] == r1.get(m, 0) and e["rank2"] == r2.get(m, 0), m
+    s.close()
