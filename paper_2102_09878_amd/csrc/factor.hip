@@ -100,9 +100,20 @@ Handle::~Handle() {
   }
 }
 
+void Handle::drop_cg_graph() {
+  if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
+  if (cg_graph) (void)hipGraphDestroy(cg_graph);
+  cg_exec = nullptr;
+  cg_graph = nullptr;
+  cg_base = nullptr;
+}
+
 void Handle::release_device() {
   if (!dev_ready) return;
   (void)hipStreamSynchronize(stream);
+  drop_cg_graph();
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  cap_stream = nullptr;
   for (void* p : {(void*)d_ahat, (void*)d_rp, (void*)d_ci, (void*)d_ahatT, (void*)d_atp, (void*)d_ati,
                   (void*)d_init_dst, (void*)d_D, (void*)d_cg, (void*)d_vals, (void*)d_atsrc, (void*)d_flag,
                   (void*)d_segc, (void*)d_segr, (void*)d_act, (void*)d_pqr_err})
@@ -1526,6 +1537,29 @@ void Factorizer<T>::build_apply() {
   H.d_awork = max_work > 0 ? static_cast<double*>(H.arena.alloc(max_work * sizeof(double))) : nullptr;
   H.nstage_elems = max_stage;
   H.awork_elems = max_work;
+  // launch arguments of the W sweeps (FNV-1a over pointers and sizes)
+  uint64_t key = 1469598103934665603ull;
+  auto mix = [&key](uint64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      key ^= (v >> (8 * b)) & 0xff;
+      key *= 1099511628211ull;
+    }
+  };
+  mix(H.precision);
+  mix((uint64_t)(uintptr_t)H.d_nstage);
+  mix((uint64_t)(uintptr_t)H.d_awork);
+  for (const ApplyBatch& b : H.batches) {
+    mix((uint64_t)(uintptr_t)b.d_ops);
+    mix((uint64_t)b.n);
+    mix((uint64_t)b.max_n1);
+    mix((uint64_t)(uintptr_t)b.d_nslots);
+    mix((uint64_t)(uintptr_t)b.d_nptr);
+    mix((uint64_t)(uintptr_t)b.d_noff);
+    mix((uint64_t)b.n_nslots);
+    mix((uint64_t)(uintptr_t)b.d_chunks);
+    mix((uint64_t)b.nchunks);
+  }
+  H.apply_key = key;
 }
 
 template <typename T>
@@ -1627,6 +1661,7 @@ void factorize(Handle& H, double eps, const int* forced, int nforced) {
   if (!(eps >= 0.0)) throw Error(SPAQR_EARG, "eps must be >= 0");
   H.ensure_device();
   H.factored = false;
+  ++H.factor_gen;
   SPAQR_HIP(hipStreamSynchronize(H.stream));
   H.arena.reset();
   H.kt.used = 0;
@@ -1645,39 +1680,48 @@ void factorize(Handle& H, double eps, const int* forced, int nforced) {
   H.factored = true;
 }
 
-void apply_op(Handle& H, bool transpose, double* x, double* stage, double* work, bool timing) {
+void apply_op_stream(Handle& H, bool transpose, double* x, double* stage, double* work, bool timing,
+                     hipStream_t st) {
   if (!stage) stage = H.d_nstage;
   if (!work) work = H.d_awork;
   const int nb = (int)H.batches.size();
   for (int k = 0; k < nb; ++k) {
     const ApplyBatch& b = H.batches[transpose ? k : nb - 1 - k];
     const bool timed = timing && H.kt.pick("apply");
-    if (timed) H.kt.mark(H.stream);
+    if (timed) H.kt.mark(st);
     const bool f32 = H.precision == SPAQR_FP32_FACTOR;
     if (!transpose && b.nchunks > 0) {
       if (f32)
-        launch_apply_gemv<float>(b.d_ops, b.d_chunks, b.nchunks, false, x, stage, work, H.stream);
+        launch_apply_gemv<float>(b.d_ops, b.d_chunks, b.nchunks, false, x, stage, work, st);
       else
-        launch_apply_gemv<double>(b.d_ops, b.d_chunks, b.nchunks, false, x, stage, work, H.stream);
+        launch_apply_gemv<double>(b.d_ops, b.d_chunks, b.nchunks, false, x, stage, work, st);
     }
     if (f32)
-      launch_apply_batch<float>(b.d_ops, b.n, b.max_n1, transpose, x, stage, work, H.stream);
+      launch_apply_batch<float>(b.d_ops, b.n, b.max_n1, transpose, x, stage, work, st);
     else
-      launch_apply_batch<double>(b.d_ops, b.n, b.max_n1, transpose, x, stage, work, H.stream);
+      launch_apply_batch<double>(b.d_ops, b.n, b.max_n1, transpose, x, stage, work, st);
     if (transpose && b.nchunks > 0) {
       if (f32)
-        launch_apply_gemv<float>(b.d_ops, b.d_chunks, b.nchunks, true, x, stage, work, H.stream);
+        launch_apply_gemv<float>(b.d_ops, b.d_chunks, b.nchunks, true, x, stage, work, st);
       else
-        launch_apply_gemv<double>(b.d_ops, b.d_chunks, b.nchunks, true, x, stage, work, H.stream);
+        launch_apply_gemv<double>(b.d_ops, b.d_chunks, b.nchunks, true, x, stage, work, st);
     }
     if (transpose && b.n_nslots > 0)
-      launch_apply_nsum(b.d_nslots, b.d_nptr, b.d_noff, b.n_nslots, stage, x, H.stream);
+      launch_apply_nsum(b.d_nslots, b.d_nptr, b.d_noff, b.n_nslots, stage, x, st);
     if (timed) {
-      H.kt.mark(H.stream);
+      H.kt.mark(st);
       H.kt.bytes += b.bytes;
       H.kt.flops += b.flops;
     }
   }
+}
+
+void apply_op(Handle& H, bool transpose, double* x, double* stage, double* work, bool timing) {
+  apply_op_stream(H, transpose, x, stage, work, timing, H.stream);
+}
+
+void apply_op_on(Handle& H, bool transpose, double* x, hipStream_t st) {
+  apply_op_stream(H, transpose, x, nullptr, nullptr, false, st);
 }
 
 }  // namespace spaqr

@@ -187,6 +187,19 @@ struct Handle {
   std::vector<int> ranks;
   spaqr_stats stats{};
   KernelTimer kt;
+  // CGLS iteration captured as a HIP graph (recorded on cap_stream, launched
+  // on stream).  Its launches depend only on the apply batches' launch
+  // arguments (apply_key, a hash of every pointer and size they pass) and
+  // on the workspace (cg_base): a refactorization that reproduces both (the
+  // same structure allocates the same addresses) keeps the graph.
+  uint64_t factor_gen = 0;
+  uint64_t apply_key = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t cg_graph = nullptr;
+  hipGraphExec_t cg_exec = nullptr;
+  uint64_t cg_key = 0;
+  const double* cg_base = nullptr;
+  void drop_cg_graph();
   // solver workspace
   double* d_cg = nullptr;
   size_t cg_elems = 0;
@@ -204,6 +217,9 @@ void factorize(Handle& H, double eps, const int* forced, int nforced);
 // skips the per-kernel timer (which may allocate event and stamp storage).
 void apply_op(Handle& H, bool transpose, double* x_dev, double* stage = nullptr, double* work = nullptr,
               bool timing = true);
+// The same on stream st, with the handle's staging and no timing (for
+// recording into a graph).
+void apply_op_on(Handle& H, bool transpose, double* x_dev, hipStream_t st);
 // CGLS on every problem of the plan at once, each with its own scalars and
 // stopping test; infos[count] (may be null).  Returns SPAQR_NOCONV if any
 // problem reached max_iter.

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "cgls.h"
@@ -236,22 +237,44 @@ int cgls(Handle& H, const double* b, double tol, int max_iter, double* x, spaqr_
   upload_act(H, act);
   int it = 0;
   std::vector<double> tt;
-  while (nact > 0 && it < max_iter) {
+  // one iteration's kernels (every argument a handle-owned pointer, so the
+  // sequence can be recorded once and replayed)
+  auto iteration = [&](hipStream_t ks) {
     // q = Ahat W^-1 p
-    launch_copy(v.u, v.p, N, st);
-    apply_op(H, false, v.u);
-    amul(H, v.u, v.q);
-    launch_sdot(v.q, nullptr, nullptr, sr, v.part, v.sc, SC_QQ, st);
-    launch_step(v.y, v.p, sc, v.r, v.q, sr, H.d_act, v.sc, st);
+    launch_copy(v.u, v.p, N, ks);
+    apply_op_on(H, false, v.u, ks);
+    launch_spmv(H.d_rp, H.d_ci, H.d_ahat, v.u, v.q, H.P.M, ks);
+    launch_sdot(v.q, nullptr, nullptr, sr, v.part, v.sc, SC_QQ, ks);
+    launch_step(v.y, v.p, sc, v.r, v.q, sr, H.d_act, v.sc, ks);
     // t = Ahat^T r, ||A^T r|| = ||D t||
-    atmul(H, v.r, v.t);
-    launch_sdot(v.t, nullptr, H.d_D, sc, v.part, v.sc, SC_TT, st);
+    launch_spmv(H.d_atp, H.d_ati, H.d_ahatT, v.r, v.t, H.P.N, ks);
+    launch_sdot(v.t, nullptr, H.d_D, sc, v.part, v.sc, SC_TT, ks);
     // s = W^-T t, p = s + beta p
-    launch_copy(v.s, v.t, N, st);
-    apply_op(H, true, v.s);
-    launch_sdot(v.s, nullptr, nullptr, sc, v.part, v.sc, SC_GN, st);
-    launch_pupdate(v.p, v.s, sc, H.d_act, v.sc, st);
-    launch_set(v.sc, SC_G, SC_GN, H.d_act, G, st);
+    launch_copy(v.s, v.t, N, ks);
+    apply_op_on(H, true, v.s, ks);
+    launch_sdot(v.s, nullptr, nullptr, sc, v.part, v.sc, SC_GN, ks);
+    launch_pupdate(v.p, v.s, sc, H.d_act, v.sc, ks);
+    launch_set(v.sc, SC_G, SC_GN, H.d_act, G, ks);
+  };
+  // CGLS iterations replay one captured HIP graph (SPAQR_NO_GRAPH=1 keeps
+  // the eager launches, which run the same kernels in the same order)
+  const bool no_graph = std::getenv("SPAQR_NO_GRAPH") != nullptr;
+  const bool graph = !no_graph && !H.kt.on("apply") && nact > 0 && max_iter > 0;
+  if (graph && (!H.cg_exec || H.cg_key != H.apply_key || H.cg_base != H.d_cg)) {
+    H.drop_cg_graph();
+    if (!H.cap_stream) SPAQR_HIP(hipStreamCreateWithFlags(&H.cap_stream, hipStreamNonBlocking));
+    SPAQR_HIP(hipStreamBeginCapture(H.cap_stream, hipStreamCaptureModeRelaxed));
+    iteration(H.cap_stream);
+    SPAQR_HIP(hipStreamEndCapture(H.cap_stream, &H.cg_graph));
+    SPAQR_HIP(hipGraphInstantiate(&H.cg_exec, H.cg_graph, nullptr, nullptr, 0));
+    H.cg_key = H.apply_key;
+    H.cg_base = H.d_cg;
+  }
+  while (nact > 0 && it < max_iter) {
+    if (graph)
+      SPAQR_HIP(hipGraphLaunch(H.cg_exec, st));
+    else
+      iteration(st);
     ++it;
     read_slot(H, v.sc, SC_TT, tt);
     nact = 0;
