@@ -105,6 +105,18 @@ typedef struct {
   int64_t level_rank2[SPAQR_MAX_LEVELS];      /* sum of step-2 ranks (columns kept)    */
 } spaqr_stats;
 
+/* Launch shapes of the factorization (see spaqr_autotune). */
+typedef struct {
+  int32_t pqr_poll;        /* pivot steps between host polls of a rank-revealing-QR batch (default 16) */
+  int32_t pqr_reg_rows;    /* tallest row window a pivot step keeps in registers, 0..1024 (1024)      */
+  int32_t tall_coop;       /* 1: tall FP32 panels in one cooperative launch; 0: two per column (1)   */
+  int32_t from_cache;      /* spaqr_autotune: 1 if the choice was read from the cache file           */
+  int32_t evaluations;     /* settings timed when it was tuned                                        */
+  int32_t pad_;
+  double seconds_default;  /* best factorization time with the defaults when it was tuned            */
+  double seconds_best;     /* best factorization time with the chosen shapes                          */
+} spaqr_tune;
+
 typedef struct {
   int32_t kind;   /* 0 eliminate (R_ss, R_sN), 1 scale (R_pp), 2 sparsify (Q_pp reflectors) */
   int32_t n1;     /* eliminate: c_s;  scale: c_p;  sparsify: c_p                          */
@@ -263,6 +275,27 @@ int spaqr_get_ranks(spaqr_handle h, int32_t* ranks, int32_t cap, int32_t* n);
  * Any output pointer may be NULL. */
 int spaqr_get_op(spaqr_handle h, int32_t i, spaqr_op_desc* desc, double* mat, int32_t* slots1,
                  int32_t* slots2, double* tau);
+
+/* Project-written autotuner of the launch shapes for this handle's
+ * problem (the batching form's tile choice): it times whole
+ * factorizations with eps (the best of reps >= 1 runs per setting),
+ * descends one knob at a time from the defaults (poll interval 4 / 16 /
+ * 64 steps; register window 256 / 512 / 1024 rows; cooperative or
+ * two-launch tall FP32 panels), keeps the fastest, and leaves the handle
+ * factorized with it.  cache_path (may be NULL): a text file of
+ * "signature poll rows coop t_default t_best evaluations" lines; an entry
+ * whose signature (M, N, nnz, depth, skip, members, precision, eps, GPU
+ * architecture) matches is used without timing, a new choice is appended.
+ * The knobs change no result beyond the rounding of the panel form.
+ * out (may be NULL) receives the choice.  SPAQR_EARG for reps < 1 or an
+ * unwritable cache. */
+int spaqr_autotune(spaqr_handle h, double eps, int32_t reps, const char* cache_path, spaqr_tune* out);
+
+/* Set (validated: 1 <= pqr_poll <= 4096, 0 <= pqr_reg_rows <= 1024,
+ * tall_coop 0 or 1; other fields ignored) or read the launch shapes;
+ * they apply from the next factorization. */
+int spaqr_set_tune(spaqr_handle h, const spaqr_tune* t);
+int spaqr_get_tune(spaqr_handle h, spaqr_tune* out);
 
 /* Release every resource of the handle. */
 int spaqr_destroy(spaqr_handle h);

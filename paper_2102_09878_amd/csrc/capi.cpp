@@ -126,6 +126,38 @@ int spaqr_csne(spaqr_handle h, const double* b_dev, double tol, int32_t max_step
   });
 }
 
+int spaqr_autotune(spaqr_handle h, double eps, int32_t reps, const char* cache_path, spaqr_tune* out) {
+  return guard(h, [&]() -> int {
+    if (!h) throw spaqr::Error(SPAQR_EARG, "null handle");
+    spaqr::autotune(h->h, eps, reps, cache_path, out);
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_set_tune(spaqr_handle h, const spaqr_tune* t) {
+  return guard(h, [&]() -> int {
+    if (!h || !t) throw spaqr::Error(SPAQR_EARG, "null argument");
+    spaqr::TuneParams p;
+    p.pqr_poll = t->pqr_poll;
+    p.pqr_reg_rows = t->pqr_reg_rows;
+    p.tall_coop = t->tall_coop;
+    spaqr::check_tune(p);
+    h->h.tune = p;
+    return SPAQR_OK;
+  });
+}
+
+int spaqr_get_tune(spaqr_handle h, spaqr_tune* out) {
+  return guard(h, [&]() -> int {
+    if (!h || !out) throw spaqr::Error(SPAQR_EARG, "null argument");
+    *out = spaqr_tune{};
+    out->pqr_poll = h->h.tune.pqr_poll;
+    out->pqr_reg_rows = h->h.tune.pqr_reg_rows;
+    out->tall_coop = h->h.tune.tall_coop;
+    return SPAQR_OK;
+  });
+}
+
 int spaqr_apply_noalloc(spaqr_handle h, const double* b_dev, double* x_dev) {
   return guard(h, [&]() -> int {
     if (!h || !b_dev || !x_dev) throw spaqr::Error(SPAQR_EARG, "null argument");

@@ -548,10 +548,11 @@ class Factorizer {
       const bool timed = H.kt.pick("pqr_step");
       unsigned long long* stamp = timed ? H.kt.stamp(st) : nullptr;
       if (timed) timed_steps_.push_back(steps);
-      launch_pqr_step<T>(dblk, total, total, states, parts, frop, dmap, active, steps, eps_, max_m, cw, stamp, st);
+      launch_pqr_step<T>(dblk, total, total, states, parts, frop, dmap, active, steps, eps_, max_m, cw,
+                         H.tune.pqr_reg_rows, stamp, st);
       ++launches_;
       ++steps;
-      if (steps % 16 == 0 && steps < kmax) {
+      if (steps % H.tune.pqr_poll == 0 && steps < kmax) {
         SPAQR_HIP(hipMemcpyAsync(h_active, active, sizeof(int), hipMemcpyDeviceToHost, st));
         sync();
         if (*h_active == 0) break;
@@ -585,7 +586,7 @@ class Factorizer {
     ws.gp = scratch(qrpool_, 4, nf * ws.MS * QR_NB * QR_NB);
     ws.wp = scratch(qrpool_, 5, nf * ws.MT * ws.MS * QR_NB * QR_TN);
     ws.w = scratch(qrpool_, 6, nf * ws.MT * QR_NB * QR_TN);
-    launch_qr<T>(d, q, ws, st, &launches_, &H.kt);
+    launch_qr<T>(d, q, ws, st, &launches_, &H.kt, H.tune.tall_coop != 0);
   }
 
   int* flags_ = nullptr;

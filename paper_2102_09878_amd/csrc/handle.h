@@ -149,8 +149,16 @@ struct KernelTimer {
   }
 };
 
+// Launch shapes chosen per problem by spaqr_autotune (defaults otherwise).
+struct TuneParams {
+  int pqr_poll = 16;        // pivot steps between host polls of the live-matrix count
+  int pqr_reg_rows = 1024;  // tallest 64-aligned window kept in registers by a pivot step
+  int tall_coop = 1;        // tall FP32 panels in one cooperative launch (else two launches per column)
+};
+
 struct Handle {
   std::string err;
+  TuneParams tune;
   spaqr_options opt{};
   Plan P;
   hipStream_t stream = nullptr;
@@ -234,6 +242,8 @@ void csne_noalloc(Handle& H, const double* b, double* x);
 // Column scaling of the current device values d_vals: D, Ahat, Ahat^T and
 // the ||A||_2 estimate, all on the device.
 void scale_values(Handle& H);
+void check_tune(const TuneParams& t);
+void autotune(Handle& H, double eps, int reps, const char* cache_path, spaqr_tune* out);
 int adjoint(Handle& H, const double* x, const double* b, const double* g, double tol, int max_iter,
             double* grad_b, double* grad_vals, double* lambda, spaqr_cgls_info* info);
 

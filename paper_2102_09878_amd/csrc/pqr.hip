@@ -862,16 +862,19 @@ void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPa
 template <typename T>
 void launch_pqr_step(const PQRDesc* d_blk, int nblocks, int total_parts, PQRState* states,
                      PQRPart* parts, const double* frop, const int2* bmap, int* active, int i, double eps,
-                     int max_m, int cw, unsigned long long* stamp, hipStream_t s) {
+                     int max_m, int cw, int reg_rows, unsigned long long* stamp, hipStream_t s) {
   if (nblocks <= 0) return;
   const size_t lds = (size_t)std::max(1, max_m) * sizeof(double);
   if (lds > 64 * 1024) throw Error(SPAQR_EARG, "rank-revealing QR block taller than 8192 rows");
   const int rows = max_m - (i & ~63);
+  const bool regs = rows <= std::min(reg_rows, 1024);
 #define SPAQR_PQR_GO(Q, C)                                                                                   \
   hipLaunchKernelGGL((k_pqr_step<T, Q, C>), dim3(nblocks), dim3(BS), lds, s, d_blk, states, parts, total_parts,  \
                      frop, bmap, active, i, eps, stamp)
   if (cw == PQR_CW) {
-    if (rows <= 128)
+    if (!regs)
+      SPAQR_PQR_GO(0, PQR_CW / 4);
+    else if (rows <= 128)
       SPAQR_PQR_GO(2, PQR_CW / 4);
     else if (rows <= 192)
       SPAQR_PQR_GO(3, PQR_CW / 4);
@@ -995,7 +998,7 @@ void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int st
 #define SPAQR_PQR_INST(T)                                                                             \
   template void launch_pqr_init<T>(const PQRDesc*, int, PQRState*, PQRPart*, double*, const int2*, hipStream_t); \
   template void launch_pqr_step<T>(const PQRDesc*, int, int, PQRState*, PQRPart*, const double*, const int2*,  \
-                                   int*, int, double, int, int, unsigned long long*, hipStream_t);              \
+                                   int*, int, double, int, int, int, unsigned long long*, hipStream_t);         \
   template void launch_pqr_finish<T>(const PQRDesc*, int, PQRState*, int, hipStream_t);                   \
   template int pqr_run_width<T>(int, const std::vector<int>&, int*);                                     \
   template void launch_pqr_run<T>(const PQRDesc*, int, const int2*, const PQRXch&, double, int,            \

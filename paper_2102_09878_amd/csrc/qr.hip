@@ -999,7 +999,7 @@ void qr_work_dims(const std::vector<QRDesc>& h, int* MS, int* MT) {
 
 template <typename T>
 void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork& ws, hipStream_t s,
-               int* launches, KernelTimer* kt) {
+               int* launches, KernelTimer* kt, bool allow_coop) {
   if (h.empty()) return;
   const unsigned nf = (unsigned)h.size();
   int kmax = 0, mmax = 0;
@@ -1024,7 +1024,7 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork&
     // SPAQR_NO_COOP=1 keeps tall panels on the two-launches-per-column path
     // (for tools that cannot follow cooperative launches)
     static const bool no_coop = std::getenv("SPAQR_NO_COOP") != nullptr;
-    if (split && sizeof(T) == 4 && !no_coop) {
+    if (split && sizeof(T) == 4 && !no_coop && allow_coop) {
       coop_segs = (mmax - j0 + TSEG - 1) / TSEG;
       static int max_coop = -1;
       if (max_coop < 0) {
@@ -1096,8 +1096,8 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork&
 }
 
 template void launch_qr<double>(const QRDesc*, const std::vector<QRDesc>&, const QRWork&, hipStream_t, int*,
-                                KernelTimer*);
+                                KernelTimer*, bool);
 template void launch_qr<float>(const QRDesc*, const std::vector<QRDesc>&, const QRWork&, hipStream_t, int*,
-                               KernelTimer*);
+                               KernelTimer*, bool);
 
 }  // namespace spaqr

@@ -314,9 +314,12 @@ void qr_work_dims(const std::vector<QRDesc>& h, int* MS, int* MT);
 template <typename T>
 // kt (may be null): the handle's kernel timer; family "qrp_coop" brackets
 // every cooperative tall-panel launch with events.
+// allow_coop: tall FP32 panels may use the cooperative one-launch form.
 void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h_desc, const QRWork& ws, hipStream_t s,
-               int* launches, KernelTimer* kt);
+               int* launches, KernelTimer* kt, bool allow_coop);
 // Column-pivoted QR of a batch, one launch per pivot step (columns split in
+// chunks of PQR_CW; the columns stay in registers while the step's 64-aligned
+// row window is at most reg_rows rows, 1024 at most)
 // chunks of PQR_CW over work-groups).  The caller provides device scratch:
 // states (2 per matrix), parts (2 per chunk), frop (squared Frobenius norm
 // per chunk, one per chunk), bmap (one int2 per chunk) and an `active`
@@ -333,8 +336,8 @@ void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPa
                      const int2* bmap, hipStream_t s);
 template <typename T>
 void launch_pqr_step(const PQRDesc* d_blk, int nblocks, int total_parts, PQRState* states,
-                     PQRPart* parts, const double* frop, const int2* bmap, int* active, int i, double eps, int max_m, int cw,
-                     unsigned long long* stamp, hipStream_t s);
+                     PQRPart* parts, const double* frop, const int2* bmap, int* active, int i, double eps,
+                     int max_m, int cw, int reg_rows, unsigned long long* stamp, hipStream_t s);
 template <typename T>
 void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int steps, hipStream_t s);
 // Persistent form: all pivot steps of a batch in one cooperative launch of

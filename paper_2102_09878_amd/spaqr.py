@@ -24,7 +24,8 @@ MAX_LEVELS = 32
 EXPORTS = ["spaqr_analyze", "spaqr_get_ordering", "spaqr_set_values", "spaqr_factorize",
            "spaqr_factorize_forced", "spaqr_apply", "spaqr_apply_noalloc", "spaqr_csne", "spaqr_apply_op", "spaqr_cgls", "spaqr_factor_stats",
            "spaqr_get_ranks", "spaqr_get_op", "spaqr_time_kernel", "spaqr_adjoint", "spaqr_batch_analyze",
-           "spaqr_batch_info", "spaqr_batch_cgls", "spaqr_destroy", "spaqr_last_error"]
+           "spaqr_batch_info", "spaqr_batch_cgls", "spaqr_autotune", "spaqr_set_tune", "spaqr_get_tune",
+           "spaqr_destroy", "spaqr_last_error"]
 
 
 class Options(ctypes.Structure):
@@ -51,6 +52,12 @@ class Stats(ctypes.Structure):
                 ("level_interfaces", ctypes.c_int32 * MAX_LEVELS), ("level_aspect", ctypes.c_double * MAX_LEVELS),
                 ("level_cols", ctypes.c_int64 * MAX_LEVELS), ("level_rank1", ctypes.c_int64 * MAX_LEVELS),
                 ("level_rank2", ctypes.c_int64 * MAX_LEVELS)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("pqr_poll", ctypes.c_int32), ("pqr_reg_rows", ctypes.c_int32), ("tall_coop", ctypes.c_int32),
+                ("from_cache", ctypes.c_int32), ("evaluations", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("seconds_default", ctypes.c_double), ("seconds_best", ctypes.c_double)]
 
 
 class OpDesc(ctypes.Structure):
@@ -91,6 +98,9 @@ def load(path: str = LIB_PATH):
         "spaqr_batch_analyze": [I32, P, P, P, P, P, P, ctypes.POINTER(P)],
         "spaqr_batch_info": [P, ctypes.POINTER(I32), P, P],
         "spaqr_batch_cgls": [P, P, D, I32, P, P],
+        "spaqr_autotune": [P, D, I32, ctypes.c_char_p, ctypes.POINTER(Tune)],
+        "spaqr_set_tune": [P, ctypes.POINTER(Tune)],
+        "spaqr_get_tune": [P, ctypes.POINTER(Tune)],
         "spaqr_destroy": [P],
     }
     for name, args in sig.items():
@@ -314,6 +324,33 @@ def spaqr_time_kernel(h, family, every=1):
     _check(lib, h, lib.spaqr_time_kernel(h, family.encode() if family else None, int(every)))
 
 
+def _tune_dict(t):
+    return dict(pqr_poll=t.pqr_poll, pqr_reg_rows=t.pqr_reg_rows, tall_coop=t.tall_coop,
+                from_cache=bool(t.from_cache), evaluations=t.evaluations, seconds_default=t.seconds_default,
+                seconds_best=t.seconds_best)
+
+
+def spaqr_autotune(h, eps, reps=2, cache_path=None):
+    lib = load()
+    t = Tune()
+    _check(lib, h, lib.spaqr_autotune(h, float(eps), int(reps), cache_path.encode() if cache_path else None,
+                                      ctypes.byref(t)))
+    return _tune_dict(t)
+
+
+def spaqr_set_tune(h, pqr_poll=16, pqr_reg_rows=1024, tall_coop=1):
+    lib = load()
+    t = Tune(int(pqr_poll), int(pqr_reg_rows), int(tall_coop), 0, 0, 0, 0.0, 0.0)
+    _check(lib, h, lib.spaqr_set_tune(h, ctypes.byref(t)))
+
+
+def spaqr_get_tune(h):
+    lib = load()
+    t = Tune()
+    _check(lib, h, lib.spaqr_get_tune(h, ctypes.byref(t)))
+    return _tune_dict(t)
+
+
 def spaqr_destroy(h):
     lib = load()
     return lib.spaqr_destroy(h)
@@ -390,6 +427,19 @@ class Solver:
         out = torch.empty_like(v_dev)
         spaqr_apply_op(self.h, op, v_dev, out)
         return out
+
+    def autotune(self, eps, reps=2, cache_path=None):
+        """Tune the launch shapes for this problem (leaves it factorized)."""
+        self.version += 1
+        return spaqr_autotune(self.h, eps, reps, cache_path)
+
+    def set_tune(self, **kw):
+        """Change some launch shapes (pqr_poll, pqr_reg_rows, tall_coop); the rest stay."""
+        cur = spaqr_get_tune(self.h)
+        spaqr_set_tune(self.h, **{k: kw.get(k, cur[k]) for k in ("pqr_poll", "pqr_reg_rows", "tall_coop")})
+
+    def get_tune(self):
+        return spaqr_get_tune(self.h)
 
     def stats(self):
         return spaqr_factor_stats(self.h)

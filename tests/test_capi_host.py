@@ -163,3 +163,18 @@ def test_batch_rejects_mixed_skip_and_bad_member():
     with pytest.raises(pk.SpaqrError) as e:
         pk.BatchSolver([member(p1), member(p2, (24, 23))], [4, 4], skip=1)
     assert e.value.code == b.EARG and "batch member 1" in str(e.value)
+
+
+def test_set_tune_validates_without_gpu():
+    p = grid_ls((8, 8), 64, 0)
+    s = pk.Solver.from_problem(p, 2, 1)
+    assert s.get_tune() == dict(pqr_poll=16, pqr_reg_rows=1024, tall_coop=1, from_cache=False, evaluations=0,
+                                seconds_default=0.0, seconds_best=0.0)
+    for bad in (dict(pqr_poll=0), dict(pqr_reg_rows=2048), dict(tall_coop=3)):
+        with pytest.raises(pk.SpaqrError) as e:
+            s.set_tune(**bad)
+        assert e.value.code == b.EARG
+    s.set_tune(pqr_poll=4)
+    assert s.get_tune()["pqr_poll"] == 4 and s.get_tune()["pqr_reg_rows"] == 1024
+    s.close()
+
