@@ -36,7 +36,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.linalg as sl
 
-from . import dense, nd
+from . import dense, graph_nd, nd
 
 UNIT_ROUNDOFF = np.finfo(np.float64).eps / 2
 
@@ -122,12 +122,49 @@ def _ancestor_or_self(a: nd.NDNode, b: nd.NDNode) -> bool:
     return (b.path >> (b.level - a.level)) == a.path
 
 
+def _graph_clusters(prob, depth):
+    """Tree, clusters and matching for a matrix without a grid (readings G1-G3
+    of oracle.graph_nd)."""
+    adj_ptr, adj_idx = graph_nd.column_graph(prob.M, prob.N, np.asarray(prob.row_ptr), np.asarray(prob.col_idx))
+    try:
+        nodes = graph_nd.build_tree(prob.N, adj_ptr, adj_idx, depth)
+    except ValueError as e:
+        raise SpaqrError(str(e))
+    for S in nodes:
+        sets = graph_nd.piece_sets(S, depth, adj_ptr, adj_idx, prob.N)
+        S.pieces = {}
+        for g, lst in sets.items():
+            S.pieces[g] = [Cluster(key=(S.rank, cols[0]), sep=S, gran=g, lo=None, hi=None, slots=list(cols))
+                           for cols in lst]
+        for g in range(S.level, max(sets)):
+            where = {j: P for P in S.pieces[g] for j in P.slots}
+            for c in S.pieces[g + 1]:
+                par = {id(where[j]) for j in c.slots}
+                if len(par) != 1:
+                    raise SpaqrError("interface hierarchy does not nest")
+                c.parent = where[c.slots[0]]
+                c.parent.children.append(c)
+        S.finest = S.pieces[max(sets)]
+    try:
+        match = graph_nd.max_product_matching(prob.M, prob.N, np.asarray(prob.row_ptr), np.asarray(prob.col_idx),
+                                              np.asarray(prob.vals))
+    except ValueError as e:
+        raise SpaqrError(str(e))
+    return nodes, match
+
+
 def analyze(prob, depth: int, w: int = 2) -> Analysis:
-    """Ordering, interfaces, hierarchy and row ownership (Section 2.2)."""
-    grid = tuple(prob.grid) + (1,) * (3 - len(prob.grid))
+    """Ordering, interfaces, hierarchy and row ownership (Section 2.2).
+
+    With a cell grid the partition is geometric (oracle.nd); without one
+    (prob.grid None) it is the graph nested dissection of oracle.graph_nd,
+    with the max-product row matching."""
     M, N = prob.M, prob.N
     if M < N:
         raise SpaqrError("M < N")
+    if getattr(prob, "grid", None) is None:
+        return _analyze_general(prob, depth)
+    grid = tuple(prob.grid) + (1,) * (3 - len(prob.grid))
     nodes = nd.build_tree(grid, depth, w)
     # clusters for every separator at every granularity it takes
     for S in nodes:
@@ -160,6 +197,28 @@ def analyze(prob, depth: int, w: int = 2) -> Analysis:
     if any(c is None for c in col_cluster):
         raise SpaqrError("cell in no cluster")
 
+    match = np.arange(N, dtype=np.int64)   # column j <-> its Laplacian row j (reading R3)
+    return _finish(prob, depth, w, grid, nodes, finest, col_cluster, match)
+
+
+def _analyze_general(prob, depth):
+    M, N = prob.M, prob.N
+    nodes, match = _graph_clusters(prob, depth)
+    finest = sorted([c for S in nodes for c in S.finest], key=_key)
+    col_cluster = [None] * N
+    for ci, c in enumerate(finest):
+        c.index = ci
+        for j in c.slots:
+            if col_cluster[j] is not None:
+                raise SpaqrError("column in two clusters")
+            col_cluster[j] = c
+    if any(c is None for c in col_cluster):
+        raise SpaqrError("column in no cluster")
+    return _finish(prob, depth, 0, None, nodes, finest, col_cluster, match)
+
+
+def _finish(prob, depth, w, grid, nodes, finest, col_cluster, match):
+    M, N = prob.M, prob.N
     # column scaling (Section 2.7)
     row_ptr = np.asarray(prob.row_ptr, dtype=np.int64)
     col_idx = np.asarray(prob.col_idx, dtype=np.int64)
@@ -179,12 +238,14 @@ def analyze(prob, depth: int, w: int = 2) -> Analysis:
                 if not (_ancestor_or_self(ns[i], ns[k]) or _ancestor_or_self(ns[k], ns[i])):
                     raise SpaqrError(f"row {r} touches two sibling subtrees")
 
-    # row ownership (Section 2.2): column j is matched to row j; every other
-    # row goes to the finest cluster holding the largest sum of its squared
-    # (scaled) entries, ties to the lowest cluster id
-    owner = np.empty(M, dtype=np.int64)
-    owner[:N] = [col_cluster[j].index for j in range(N)]
-    for r in range(N, M):
+    # row ownership (Section 2.2): the row matched to column j goes to j's
+    # cluster; every other row goes to the finest cluster holding the
+    # largest sum of its squared (scaled) entries, ties to the lowest id
+    owner = np.full(M, -1, dtype=np.int64)
+    owner[match] = [col_cluster[j].index for j in range(N)]
+    for r in range(M):
+        if owner[r] >= 0:
+            continue
         lo, hi = row_ptr[r], row_ptr[r + 1]
         acc = {}
         for j, v in zip(col_idx[lo:hi], ahat[lo:hi]):

@@ -142,6 +142,36 @@ def grid_ls(grid, extra_rows: int, seed: int, with_target: bool = False) -> Grid
                        vals=vals, b=b, x_t=x_t, seed=seed)
 
 
+def general_ls(grid, extra_rows: int, seed: int, jitter: float = 0.1) -> GridProblem:
+    """A grid problem handed over as a general sparse matrix: rows and
+    columns in random order, no grid attached (grid None), and the
+    Laplacian rows' values jittered by jitter * N(0, 1) so that no two
+    entries tie.  Draw order: the grid problem's draws (seed), then from
+    default_rng(seed + 7919): the column permutation, the row permutation,
+    the jitter.  meta keeps both permutations (col_perm[new] = old column,
+    row_perm[new] = old row)."""
+    p = grid_ls(grid, extra_rows, seed)
+    rng = np.random.default_rng(seed + 7919)
+    cp = rng.permutation(p.N)
+    rp = rng.permutation(p.M)
+    vals = p.vals.copy()
+    nlap = int(p.row_ptr[p.N])
+    vals[:nlap] += jitter * rng.standard_normal(nlap)
+    inv = np.empty(p.N, dtype=np.int64)
+    inv[cp] = np.arange(p.N)
+    A = p.scipy().tocoo()
+    rows_new = np.empty(p.M, dtype=np.int64)
+    rows_new[rp] = np.arange(p.M)
+    import scipy.sparse as sp
+    B = sp.csr_matrix((vals, (rows_new[A.row], inv[A.col])), shape=(p.M, p.N))
+    B.sort_indices()
+    q = GridProblem(grid=None, M=p.M, N=p.N, row_ptr=B.indptr.astype(np.int64),
+                    col_idx=B.indices.astype(np.int32), vals=B.data.astype(np.float64), b=p.b[rp].copy(),
+                    seed=seed)
+    q.meta = dict(kind="general", col_perm=cp, row_perm=rp, source_grid=tuple(p.grid))
+    return q
+
+
 def grid_square(grid, seed: int, skew: float = 0.3) -> GridProblem:
     """Square nonsymmetric grid system (M = N): the Laplacian's stencil
     pattern with off-diagonal values -1 + skew * N(0,1), drawn independently
