@@ -2,7 +2,8 @@
 
 * Householder reflectors in the LAPACK convention: H = I - tau v v^T with
   v[0] = 1, H x = beta e_1, beta = -sign(alpha) ||x|| with sign(0) = +1, and
-  tau = 0 when x[1:] is zero.  This is the block Householder QR used to
+  tau = 0 when x[1:] is zero; an alpha at rounding level (|alpha| <=
+  64 u ||x||) counts as 0.  This is the block Householder QR used to
   eliminate clusters (Section 2.3) and to scale interfaces (Section 2.4).
 * Column-pivoted Householder QR truncated by the paper's rank rule
   |R_ii| >= eps |R_11| (Section 4, the low-rank approximations of
@@ -23,15 +24,27 @@ import numpy as np
 EPS = np.finfo(np.float64).eps
 
 
-def house(x: np.ndarray):
-    """Return (v, tau, beta) with (I - tau v v^T) x = beta e_1, v[0] = 1."""
+# |alpha| at or below this multiple of u ||x|| is rounding error: its sign
+# carries no information and counts as +1
+SIGN_FLOOR = 64.0
+
+
+def house(x: np.ndarray, unit: float = EPS / 2):
+    """Return (v, tau, beta) with (I - tau v v^T) x = beta e_1, v[0] = 1.
+
+    LAPACK's convention beta = -sign(alpha) ||x|| with sign(0) = +1, where
+    an alpha of at most SIGN_FLOOR * unit * ||x|| counts as 0: such an
+    alpha is a structural zero carrying rounding error, and two correct
+    evaluations may give it either sign."""
     alpha = float(x[0])
     xnorm = float(np.sqrt(np.dot(x[1:], x[1:]))) if x.shape[0] > 1 else 0.0
     v = np.zeros_like(x)
     v[0] = 1.0
     if xnorm == 0.0:
         return v, 0.0, alpha
-    beta = -math.copysign(math.hypot(alpha, xnorm), alpha if alpha != 0.0 else 1.0)
+    nrm = math.hypot(alpha, xnorm)
+    sgn = alpha if abs(alpha) > SIGN_FLOOR * unit * nrm else 1.0
+    beta = -math.copysign(nrm, sgn)
     tau = (beta - alpha) / beta
     v[1:] = x[1:] / (alpha - beta)
     return v, tau, beta

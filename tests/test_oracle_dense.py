@@ -98,3 +98,24 @@ def test_rank_zero_for_zero_and_empty():
     assert dense.pivoted_qr(np.zeros((5, 4)), 1e-2)[0] == 0
     assert dense.pivoted_qr(np.zeros((5, 0)), 1e-2)[0] == 0
     assert dense.pivoted_qr(np.zeros((0, 4)), 1e-2)[0] == 0
+
+
+def test_rounding_level_alpha_takes_the_positive_sign():
+    """An alpha that is a structural zero carrying rounding error (either
+    sign) gives the same reflector as an exact zero; a genuinely small alpha
+    above the floor keeps its sign."""
+    tail = np.array([0.3, -1.2, 0.5])
+    ref = dense.house(np.concatenate([[0.0], tail]))
+    for a in (1e-22, -1e-22, -4e-17):
+        v, tau, beta = dense.house(np.concatenate([[a], tail]))
+        assert beta < 0 and abs(beta - ref[2]) <= 1e-15 and abs(tau - ref[1]) <= 1e-15
+    v, tau, beta = dense.house(np.concatenate([[-1e-9], tail]))
+    assert beta > 0
+    # the same front column with structural-zero noise of opposite signs
+    F = np.array([[-3e-21, 1.0], [0.6, 2.0], [0.8, -1.0]])
+    G = F.copy()
+    G[0, 0] = 3e-21
+    dense.householder_qr(F)
+    dense.householder_qr(G)
+    assert np.abs(np.triu(F[:2]) - np.triu(G[:2])).max() <= 1e-15
+
