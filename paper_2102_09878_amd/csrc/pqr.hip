@@ -57,6 +57,13 @@ __device__ __forceinline__ void block_argmax(double& bv, int& bi, double* shv, i
     if (shv[w] > bv || (shv[w] == bv && shi[w] < bi)) bv = shv[w], bi = shi[w];
 }
 
+// Reflector scalars in LAPACK's convention (beta = -sign(alpha) ||x||,
+// sign(0) = +1), where an alpha of at most SIGN_FLOOR u ||x|| (u the FP64
+// unit roundoff, whatever the storage type) counts as 0: it is a structural
+// zero carrying rounding error, whose sign two evaluations may not agree
+// on.  (FP32 rounding can exceed that floor; there the FP32 form may flip
+// an R row relative to the FP64 form: an equivalent factor.)
+constexpr double SIGN_FLOOR = 64.0 * 1.1102230246251565e-16;
 __device__ __forceinline__ void house_scalars(double alpha, double xn2, double& beta, double& tau,
                                               double& scal) {
   if (xn2 == 0.0) {
@@ -64,8 +71,9 @@ __device__ __forceinline__ void house_scalars(double alpha, double xn2, double& 
     tau = 0.0;
     scal = 1.0;
   } else {
-    const double s = alpha < 0.0 ? -1.0 : 1.0;
-    beta = -s * sqrt(alpha * alpha + xn2);
+    const double nrm = sqrt(alpha * alpha + xn2);
+    const double s = (alpha < 0.0 && -alpha > SIGN_FLOOR * nrm) ? -1.0 : 1.0;
+    beta = -s * nrm;
     tau = (beta - alpha) / beta;
     scal = 1.0 / (alpha - beta);
   }
