@@ -27,7 +27,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result", f"-I{os.p
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-SOURCES = ["analyze.cpp", "capi.cpp", "solve.cpp", "tune.cpp", "factor.hip", "kernels.hip", "qr.hip", "pqr.hip", "apply.hip", "cgls.hip", "adjoint.hip", "noalloc.hip"]
+SOURCES = ["analyze.cpp", "graph_nd.cpp", "capi.cpp", "solve.cpp", "tune.cpp", "factor.hip", "kernels.hip", "qr.hip", "pqr.hip", "apply.hip", "cgls.hip", "adjoint.hip", "noalloc.hip"]
 
 
 def _compile(src: str, debug: bool) -> str:

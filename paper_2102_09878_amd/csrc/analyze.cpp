@@ -171,6 +171,9 @@ bool ancestor_or_self(const NDNode& a, const NDNode& b) {
   return (b.path >> (b.level - a.level)) == a.path;
 }
 
+// geometric tree, interfaces, hierarchy and finest clusters (below)
+void build_geometric(Plan& P);
+
 }  // namespace
 
 void rescale_values(Plan& P, const double* vals) {
@@ -191,11 +194,14 @@ void analyze_plan(Plan& P, const int64_t* row_ptr, const int32_t* col_idx, const
   if (N < 1 || M < N) throw Error(SPAQR_EARG, "need M >= N >= 1");
   P.M = M;
   P.N = N;
-  for (int a = 0; a < 3; ++a) P.grid[a] = opt.grid[a] > 0 ? opt.grid[a] : 1;
-  if (opt.grid[0] <= 0 || opt.grid[1] <= 0)
-    throw Error(SPAQR_EARG, "geometric partitioning needs the cell grid (options.grid)");
-  if ((int64_t)P.grid[0] * P.grid[1] * P.grid[2] != N)
+  // with a cell grid the partition is geometric; without one (grid[0] <= 0)
+  // it is the graph nested dissection of graph_nd.cpp
+  const bool geometric = opt.grid[0] > 0;
+  for (int a = 0; a < 3; ++a) P.grid[a] = opt.grid[a] > 0 ? opt.grid[a] : (geometric ? 1 : 0);
+  if (geometric && opt.grid[1] <= 0) throw Error(SPAQR_EARG, "grid[1] must be positive with grid[0]");
+  if (geometric && (int64_t)P.grid[0] * P.grid[1] * P.grid[2] != N)
     throw Error(SPAQR_EARG, "grid size does not match N");
+  if (!geometric && N >= ((int64_t)1 << 31)) throw Error(SPAQR_EARG, "N too large");
   P.w = opt.sep_width > 0 ? opt.sep_width : 2;
   P.depth = opt.nd_depth > 0 ? opt.nd_depth
                              : std::max(2, (int)std::ceil(std::log2((double)N / 64.0)));
@@ -216,6 +222,22 @@ void analyze_plan(Plan& P, const int64_t* row_ptr, const int32_t* col_idx, const
   P.col_idx.assign(col_idx, col_idx + P.nnz);
   rescale_values(P, vals);
 
+  std::vector<int64_t> match;
+  if (geometric) {
+    build_geometric(P);
+    match.resize(N);
+    std::iota(match.begin(), match.end(), 0);  // column j <-> its Laplacian row j
+  } else {
+    graph_partition(P);
+    match = max_product_matching(P);
+  }
+  finish_plan(P, match);
+}
+
+namespace {
+
+void build_geometric(Plan& P) {
+  const int64_t N = P.N;
   build_tree(P);
 
   // clusters of every separator at every granularity
@@ -291,7 +313,14 @@ void analyze_plan(Plan& P, const int64_t* row_ptr, const int32_t* col_idx, const
   }
   for (int64_t j = 0; j < N; ++j)
     if (P.col_cluster[j] < 0) throw Error(SPAQR_EARG, "cell in no cluster");
+}
 
+}  // namespace
+
+void finish_plan(Plan& P, const std::vector<int64_t>& match) {
+  const int64_t M = P.M, N = P.N;
+  const int64_t* row_ptr = P.row_ptr.data();
+  const int32_t* col_idx = P.col_idx.data();
   // rows must not couple two sibling subtrees
   for (int64_t r = 0; r < M; ++r) {
     for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e)
@@ -303,11 +332,13 @@ void analyze_plan(Plan& P, const int64_t* row_ptr, const int32_t* col_idx, const
       }
   }
 
-  // row ownership: column j matched with row j; other rows to the finest
-  // cluster with the largest sum of squared scaled entries (lowest id on ties)
+  // row ownership: the row matched to column j goes to j's cluster; other
+  // rows to the finest cluster with the largest sum of squared scaled
+  // entries (lowest id on ties)
   P.row_owner.assign(M, -1);
-  for (int64_t j = 0; j < N; ++j) P.row_owner[j] = P.col_cluster[j];
-  for (int64_t r = N; r < M; ++r) {
+  for (int64_t j = 0; j < N; ++j) P.row_owner[match[j]] = P.col_cluster[j];
+  for (int64_t r = 0; r < M; ++r) {
+    if (P.row_owner[r] >= 0) continue;
     std::vector<std::pair<int, double>> acc;
     for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
       int c = P.col_cluster[col_idx[e]];

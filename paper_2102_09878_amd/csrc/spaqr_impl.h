@@ -101,6 +101,14 @@ void analyze_plan(Plan& P, const int64_t* row_ptr, const int32_t* col_idx, const
 // sparsification skip.
 void union_plans(Plan& U, std::vector<Plan>& parts);
 void rescale_values(Plan& P, const double* vals);
+// Graph nested dissection, interfaces and hierarchy for a plan without a
+// grid (fills nodes, clusters, finest, col_cluster); graph_nd.cpp.
+void graph_partition(Plan& P);
+// Row matched to every column: the assignment of largest product of |a_ij|.
+std::vector<int64_t> max_product_matching(const Plan& P);
+// Checks, row ownership (matched rows to their column's cluster, the others
+// by the max-norm rule), initial groups and the transposed pattern.
+void finish_plan(Plan& P, const std::vector<int64_t>& match);
 
 // ---------------------------------------------------------------------------
 // Device memory

@@ -148,7 +148,7 @@ def spaqr_analyze(row_ptr, col_idx, vals, M, N, grid, nd_depth=0, sparsify_skip=
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
     va = np.ascontiguousarray(vals, dtype=np.float64)
-    g = list(grid) + [1] * (3 - len(grid))
+    g = [0, 0, 0] if grid is None else list(grid) + [1] * (3 - len(grid))   # no grid: graph partitioning
     opt = Options(nd_depth, sparsify_skip, (ctypes.c_int32 * 3)(*g), sep_width, precision, device, None)
     h = ctypes.c_void_p()
     rc = lib.spaqr_analyze(_ptr(rp), _ptr(ci), _ptr(va), int(M), int(N), ctypes.byref(opt), ctypes.byref(h))
@@ -245,7 +245,7 @@ def spaqr_batch_analyze(problems, depths, sparsify_skip=-1, sep_width=0, precisi
         keep += [rp, ci, va]
         rps[g], cis[g], vas[g] = rp.ctypes.data, ci.ctypes.data, va.ctypes.data
         Ms[g], Ns[g] = M, N
-        gr = list(grid) + [1] * (3 - len(grid))
+        gr = [0, 0, 0] if grid is None else list(grid) + [1] * (3 - len(grid))
         opts[g] = Options(int(depths[g]), sparsify_skip, (ctypes.c_int32 * 3)(*gr), sep_width, precision, device,
                           None)
     h = ctypes.c_void_p()

@@ -45,6 +45,29 @@ def test_analysis_matches_oracle(cfg):
     s.close()
 
 
+@pytest.mark.parametrize("grid,depth", [((32, 32), 4), ((48, 40), 5), ((12, 12, 12), 3), ((64, 64), 6)])
+def test_graph_analysis_matches_oracle(grid, depth):
+    """Matrices without a grid: graph nested dissection, interfaces and the
+    max-product matching decide the column order and the row owners, which
+    must equal the oracle's exactly."""
+    from synth import general_ls
+    p = general_ls(grid, int(np.prod(grid)), 9)
+    s = pk.Solver(p.row_ptr, p.col_idx, p.vals, p.M, p.N, None, depth, -1)
+    perm, owner = s.ordering()
+    an = osp.analyze(p, depth)
+    assert (perm == an.col_perm).all()
+    assert (owner == an.row_owner).all()
+    s.close()
+
+
+def test_graph_analysis_rejects_too_deep_tree():
+    from synth import general_ls
+    p = general_ls((8, 8), 64, 1)
+    with pytest.raises(pk.SpaqrError) as e:
+        pk.Solver(p.row_ptr, p.col_idx, p.vals, p.M, p.N, None, 8, -1)
+    assert e.value.code == b.EARG
+
+
 @pytest.mark.parametrize("i", [0, 17, 63])
 def test_analysis_matches_oracle_batch_members(i):
     p = batch_problem(i)
