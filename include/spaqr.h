@@ -57,7 +57,9 @@ typedef struct {
   int32_t nd_depth;      /* tree levels including the leaves; 0 => ceil(log2(N/64)) (Section 4) */
   int32_t sparsify_skip; /* leaf-side levels left unsparsified; -1 => 2 (1 when depth <= 4)      */
   int32_t grid[3];       /* nx, ny, nz of the cell grid (x fastest), nz = 1 in 2D; column j is   */
-                         /* cell j.  Geometric partitioning needs the grid (Section 4.1).        */
+                         /* cell j: geometric partitioning (Section 4.1).  grid[0] = 0: a       */
+                         /* general matrix, partitioned by graph nested dissection of G(A^T A)  */
+                         /* with a max-product row matching (Section 2.2).                       */
   int32_t sep_width;     /* separator thickness in cell planes; 0 => 2                           */
   int32_t precision;     /* SPAQR_FP64 or SPAQR_FP32_FACTOR                                      */
   int32_t device;        /* HIP device ordinal                                                   */
@@ -127,14 +129,18 @@ typedef struct {
 
 /* Analysis (host only, no GPU needed): column norms of the given values
  * (Algorithm 1 scales every column to unit 2-norm before partitioning),
- * geometric nested dissection with interfaces and their hierarchy
- * (Section 2.2), row matching (column j <-> row j, the Laplacian row of
- * cell j) and max-norm assignment of the other rows (Section 2.2).  The
+ * nested dissection with interfaces and their hierarchy (Section 2.2):
+ * geometric on the cell grid, or on the column graph G(A^T A) when
+ * opt->grid[0] = 0; row matching (on a grid column j <-> row j, the
+ * Laplacian row of cell j; otherwise the matching of largest product of
+ * |a_ij|) and max-norm assignment of the other rows (Section 2.2).  The
  * device copy of the scaled matrix and the ||A||_2 estimate of the CGLS
  * stopping test are made by device kernels on first GPU use.
  * Errors: SPAQR_EARG for M < N, N < 1, a malformed CSR, an empty column, a
- * grid that does not match N or is too small for the depth, or a row that
- * couples two sibling subtrees.  On success *out owns a new handle. */
+ * grid that does not match N or is too small for the depth (a graph too
+ * small to split), a row that couples two sibling subtrees, or (no grid) an
+ * explicit zero entry or no matching that covers every column.  On success
+ * *out owns a new handle. */
 int spaqr_analyze(const int64_t* row_ptr, const int32_t* col_idx, const double* vals, int64_t M,
                   int64_t N, const spaqr_options* opt, spaqr_handle* out);
 
