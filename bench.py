@@ -261,6 +261,7 @@ def main() -> int:
     ap.add_argument("--every", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch form")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (calibrates HBM traffic counters)")
     args = ap.parse_args()
@@ -294,7 +295,7 @@ def main() -> int:
     for form in args.forms.split(","):
         s = pk.Solver.from_problem(prob, cfg["depth"], cfg["skip"], precision=form)
         # launch shapes from the project's autotuner (outside the timed region)
-        tune = s.autotune(cfg["eps"], reps=1, cache_path=TUNE_CACHE)
+        tune = None if args.no_tune else s.autotune(cfg["eps"], reps=1, cache_path=TUNE_CACHE)
         for _ in range(args.warmup):
             s.factorize(cfg["eps"])
             s.cgls(b, tol=1e-10)
