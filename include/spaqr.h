@@ -105,6 +105,7 @@ typedef struct {
   int64_t level_cols[SPAQR_MAX_LEVELS];       /* their columns before sparsification   */
   int64_t level_rank1[SPAQR_MAX_LEVELS];      /* sum of step-1 ranks (rows kept)       */
   int64_t level_rank2[SPAQR_MAX_LEVELS];      /* sum of step-2 ranks (columns kept)    */
+  double sync_wait_seconds;  /* host time spent waiting in those synchronisations   */
 } spaqr_stats;
 
 /* Launch shapes of the factorization (see spaqr_autotune). */

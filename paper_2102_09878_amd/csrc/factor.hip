@@ -292,9 +292,12 @@ class Factorizer {
   bool sparsified(int m) const { return m >= 2 && m <= P.depth - P.skip; }
 
   void sync() {
+    const double t = now_s();
     SPAQR_HIP(hipStreamSynchronize(st));
+    wait_s_ += now_s() - t;
     ++syncs_;
   }
+  double wait_s_ = 0.0;
 
   int next_forced() {
     if (!forced_) return -1;
@@ -1633,6 +1636,7 @@ void Factorizer<T>::run() {
   S.num_ranks = (int)H.ranks.size();
   S.launches = launches_;
   S.syncs = syncs_;
+  S.sync_wait_seconds = wait_s_;
   int64_t mem = 0;
   for (auto& o : H.ops) {
     if (o.kind == 0)

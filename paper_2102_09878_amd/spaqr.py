@@ -51,7 +51,7 @@ class Stats(ctypes.Structure):
                 ("kernel_flops", ctypes.c_double),
                 ("level_interfaces", ctypes.c_int32 * MAX_LEVELS), ("level_aspect", ctypes.c_double * MAX_LEVELS),
                 ("level_cols", ctypes.c_int64 * MAX_LEVELS), ("level_rank1", ctypes.c_int64 * MAX_LEVELS),
-                ("level_rank2", ctypes.c_int64 * MAX_LEVELS)]
+                ("level_rank2", ctypes.c_int64 * MAX_LEVELS), ("sync_wait_seconds", ctypes.c_double)]
 
 
 class Tune(ctypes.Structure):
@@ -284,7 +284,8 @@ def spaqr_factor_stats(h):
                 top_rows=s.top_rows, launches=s.launches, syncs=s.syncs, mem_factor=s.mem_factor,
                 device_bytes=s.device_bytes, flops=dict(zip(PHASES, s.flops)),
                 bytes=dict(zip(PHASES, s.bytes)), phase_seconds=dict(zip(PHASES, s.phase_seconds)),
-                factor_seconds=s.factor_seconds, kernel_calls=s.kernel_calls,
+                factor_seconds=s.factor_seconds, sync_wait_seconds=s.sync_wait_seconds,
+                kernel_calls=s.kernel_calls,
                 kernel_seconds=s.kernel_seconds, kernel_bytes=s.kernel_bytes, kernel_flops=s.kernel_flops,
                 levels_sparsified={m: dict(interfaces=s.level_interfaces[m], aspect=s.level_aspect[m],
                                            cols=s.level_cols[m], rank1=s.level_rank1[m], rank2=s.level_rank2[m])
