@@ -251,6 +251,71 @@ def _general_form(steps: int, warmup: int) -> dict:
             "residual": info["residual"], "converged": info["converged"]}
 
 
+def _other_configs(steps: int, warmup: int) -> dict:
+    """The remaining single-problem workloads, timed the same way (factorize
+    + CGLS to 1e-10 per step): the 32 x 32 grid in FP64, the 32^3 grid in
+    both forms, and the 128 x 128 differentiation workload (forward solve
+    and adjoint backward through the autograd function, FP32 factor)."""
+    import torch
+
+    import paper_2102_09878_amd as pk
+    from synth import CONFIGS, config_problem
+
+    out = {}
+    for cfg, forms in ((1, ("fp64",)), (3, ("fp32", "fp64"))):
+        c = CONFIGS[cfg]
+        p = config_problem(cfg)
+        b = torch.as_tensor(p.b, device="cuda")
+        for form in forms:
+            t = time.perf_counter()
+            s = pk.Solver.from_problem(p, c["depth"], c["skip"], precision=form)
+            t_an = time.perf_counter() - t
+            for _ in range(warmup):
+                s.factorize(c["eps"])
+                s.cgls(b, tol=1e-10, max_iter=500)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fs = cs = 0.0
+            for _ in range(steps):
+                s.factorize(c["eps"])
+                fs += s.stats()["factor_seconds"]
+                x, info = s.cgls(b, tol=1e-10, max_iter=500)
+                cs += info["seconds"]
+            torch.cuda.synchronize()
+            out[f"{c['name']}_{form}"] = dict(
+                analyze_s=t_an, s_per_step=(time.perf_counter() - t0) / steps, factor_s=fs / steps,
+                cgls_s=cs / steps, cgls_iters=info["iters"], residual=info["residual"],
+                converged=info["converged"], depth=c["depth"], eps=c["eps"])
+            s.close()
+    c = CONFIGS[5]
+    p = config_problem(5)
+    s = pk.Solver.from_problem(p, c["depth"], c["skip"], precision="fp32")
+    vals = torch.as_tensor(p.vals, device="cuda")
+    b = torch.as_tensor(p.b, device="cuda")
+    xt = torch.as_tensor(p.x_t, device="cuda")
+
+    def step():
+        v = vals.clone().requires_grad_(True)
+        bb = b.clone().requires_grad_(True)
+        x = pk.lstsq(s, v, bb, c["eps"], tol=1e-10)
+        loss = 0.5 * ((x - xt) ** 2).sum()
+        loss.backward()
+        return v.grad, bb.grad
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gv, gb = step()
+    torch.cuda.synchronize()
+    out[f"{c['name']}_fp32"] = dict(
+        s_per_step=(time.perf_counter() - t0) / steps, what="factorize + CGLS forward, adjoint CG backward",
+        grad_finite=bool(torch.isfinite(gv).all() and torch.isfinite(gb).all()))
+    s.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,6 +436,7 @@ def main() -> int:
     square = None if args.no_batch else _square_form(extra_steps, args.warmup)
     invpoi = None if args.no_batch else _inverse_poisson_form(extra_steps, args.warmup)
     general = None if args.no_batch else _general_form(extra_steps, args.warmup)
+    others = None if args.no_batch else _other_configs(extra_steps, args.warmup)
     best = min(forms, key=lambda k: forms[k]["s_per_step"] if forms[k]["converged"] else 1e30)
     bf = forms[best]
     kern = bf["kernel"]
@@ -424,6 +490,7 @@ def main() -> int:
         "square_form": square,
         "inverse_poisson_form": invpoi,
         "general_form": general,
+        "other_configs": others,
     }
     print(json.dumps(line))
     return 0
