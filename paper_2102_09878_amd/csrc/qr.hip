@@ -836,22 +836,40 @@ __global__ __launch_bounds__(BS) void k_qru_apply(const QRDesc* __restrict__ D, 
 }
 
 // ---------------------------------------------------------------------------
-// trailing update on the matrix cores (FP32 fronts)
+// trailing update on the matrix cores
 //
-// v_mfma_f32_16x16x4f32, one 16x16 block per wave: lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16] (K = 4), and holds
-// D[4 (l / 16) + v][l % 16] in accumulator v.  FP32 accumulation.
+// v_mfma_f32_16x16x4f32 (FP32 fronts) and v_mfma_f64_16x16x4f64 (FP64
+// fronts), one 16x16 block per wave: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] (K = 4), and holds D[row(l / 16, v)][l % 16] in
+// accumulator v, with row(g, v) = 4 g + v for FP32 and g + 4 v for FP64
+// (measured).  Accumulation in the storage type.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef f32x4 acc;
+  __device__ static acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int g, int v) { return 4 * g + v; }
+};
+template <>
+struct Mfma<double> {
+  typedef f64x4 acc;
+  __device__ static acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int g, int v) { return g + 4 * v; }
+};
 
 // W_s = V_s^T C_s for one (front, 64-column tile, row segment): output
 // 32 x 64; wave w computes a-rows 16 (w & 1) .. +16 and two 16-column
 // blocks 2 (w >> 1), 2 (w >> 1) + 1, over 64-row slabs staged in LDS.
+template <typename T>
 __global__ __launch_bounds__(BS) void k_qru_w_mfma(const QRDesc* __restrict__ D, int j0, QRWork ws) {
+  typedef typename Mfma<T>::acc accT;
   const QRDesc d = D[blockIdx.x];
   const int kk = min(d.m, d.k);
   if (j0 >= kk) return;
@@ -863,27 +881,27 @@ __global__ __launch_bounds__(BS) void k_qru_w_mfma(const QRDesc* __restrict__ D,
   const int r0 = max(j0, s * RS), r1 = min(m, (s + 1) * RS);
   if (r0 >= r1) return;
   const int nc = min(TN, d.n - c0);
-  const float* A = static_cast<const float*>(d.A);
+  const T* A = static_cast<const T*>(d.A);
   const int64_t lda = d.lda;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  __shared__ float Vs[64][NB + 1];
-  __shared__ float Cs[64][TN + 1];
+  __shared__ T Vs[64][NB + 1];
+  __shared__ T Cs[64][TN + 1];
   const int ab = wv & 1, jb = 2 * (wv >> 1);
   const int li = lane & 15, lk = lane >> 4;
-  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  accT acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
   // the next 64-row slab is fetched into registers while the current one
   // is multiplied out of LDS
-  float vr[64 * NB / BS], cr[64 * TN / BS];
+  T vr[64 * NB / BS], cr[64 * TN / BS];
   auto fetch = [&](int rb) {
 #pragma unroll
     for (int u = 0; u < 64 * NB / BS; ++u) {
       const int e = tid + u * BS, rr = e & 63, a = e >> 6, r = rb + rr;
-      vr[u] = r < r1 ? vref(A, lda, j0, a, kb, r) : 0.0f;
+      vr[u] = r < r1 ? vref(A, lda, j0, a, kb, r) : T(0);
     }
 #pragma unroll
     for (int u = 0; u < 64 * TN / BS; ++u) {
       const int e = tid + u * BS, rr = e & 63, cc = e >> 6, r = rb + rr;
-      cr[u] = (r < r1 && cc < nc) ? A[r + (int64_t)(c0 + cc) * lda] : 0.0f;
+      cr[u] = (r < r1 && cc < nc) ? A[r + (int64_t)(c0 + cc) * lda] : T(0);
     }
   };
   fetch(r0);
@@ -904,15 +922,15 @@ __global__ __launch_bounds__(BS) void k_qru_w_mfma(const QRDesc* __restrict__ D,
 #pragma unroll
     for (int k4 = 0; k4 < 16; ++k4) {
       const int rr = 4 * k4 + lk;
-      const float av = Vs[rr][16 * ab + li];
-      acc0 = mfma16(av, Cs[rr][16 * jb + li], acc0);
-      acc1 = mfma16(av, Cs[rr][16 * (jb + 1) + li], acc1);
+      const T av = Vs[rr][16 * ab + li];
+      acc0 = Mfma<T>::mma(av, Cs[rr][16 * jb + li], acc0);
+      acc1 = Mfma<T>::mma(av, Cs[rr][16 * (jb + 1) + li], acc1);
     }
   }
   double* out = ws.wp + (((int64_t)blockIdx.x * ws.MT + t) * ws.MS + s) * NB * TN;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int a = 16 * ab + 4 * lk + v;
+    const int a = 16 * ab + Mfma<T>::row(lk, v);
     out[a * TN + 16 * jb + li] = (double)acc0[v];
     out[a * TN + 16 * (jb + 1) + li] = (double)acc1[v];
   }
@@ -922,7 +940,9 @@ __global__ __launch_bounds__(BS) void k_qru_w_mfma(const QRDesc* __restrict__ D,
 // (W^T V_s^T)^T so that a lane's accumulators run along rows: wave w owns
 // columns 16 w .. +16 of the tile and the four 16-row blocks of each
 // 64-row slab; K = kb <= 32 in steps of 4.
+template <typename T>
 __global__ __launch_bounds__(BS) void k_qru_apply_mfma(const QRDesc* __restrict__ D, int j0, QRWork ws) {
+  typedef typename Mfma<T>::acc accT;
   const QRDesc d = D[blockIdx.x];
   const int kk = min(d.m, d.k);
   if (j0 >= kk) return;
@@ -934,30 +954,32 @@ __global__ __launch_bounds__(BS) void k_qru_apply_mfma(const QRDesc* __restrict_
   const int r0 = max(j0, s * RS), r1 = min(m, (s + 1) * RS);
   if (r0 >= r1) return;
   const int nc = min(TN, d.n - c0);
-  float* A = static_cast<float*>(d.A);
+  T* A = static_cast<T*>(d.A);
   const int64_t lda = d.lda;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  __shared__ float Ws[NB][TN + 1];
-  __shared__ float Vs[64][NB + 1];
+  __shared__ T Ws[NB][TN + 1];
+  __shared__ T Vs[64][NB + 1];
   const double* win = ws.w + ((int64_t)blockIdx.x * ws.MT + t) * NB * TN;
-  for (int e = tid; e < NB * TN; e += BS) Ws[e / TN][e % TN] = (float)win[e];
+  for (int e = tid; e < NB * TN; e += BS) Ws[e / TN][e % TN] = static_cast<T>(win[e]);
   const int li = lane & 15, lk = lane >> 4;
-  const int col = 16 * wv + 4 * lk;  // first of this lane's four columns
+  int col[4];  // this lane's four columns of the tile
+#pragma unroll
+  for (int v = 0; v < 4; ++v) col[v] = 16 * wv + Mfma<T>::row(lk, v);
   // The next slab's reflector rows and this lane's 16 entries of C are
   // fetched into registers while the current slab is multiplied.
-  float vr[64 * NB / BS], cr[4][4];
+  T vr[64 * NB / BS], cr[4][4];
   auto fetch = [&](int rb) {
 #pragma unroll
     for (int u = 0; u < 64 * NB / BS; ++u) {
       const int e = tid + u * BS, rr = e & 63, a = e >> 6, r = rb + rr;
-      vr[u] = r < r1 ? vref(A, lda, j0, a, kb, r) : 0.0f;
+      vr[u] = r < r1 ? vref(A, lda, j0, a, kb, r) : T(0);
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int r = rb + 16 * b + li;
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        cr[b][v] = (r < r1 && col + v < nc) ? A[r + (int64_t)(c0 + col + v) * lda] : 0.0f;
+        cr[b][v] = (r < r1 && col[v] < nc) ? A[r + (int64_t)(c0 + col[v]) * lda] : T(0);
     }
   };
   fetch(r0);
@@ -968,7 +990,7 @@ __global__ __launch_bounds__(BS) void k_qru_apply_mfma(const QRDesc* __restrict_
       const int e = tid + u * BS;
       Vs[e & 63][e >> 6] = vr[u];
     }
-    float cc[4][4];
+    T cc[4][4];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -977,17 +999,17 @@ __global__ __launch_bounds__(BS) void k_qru_apply_mfma(const QRDesc* __restrict_
     if (rb + 64 < r1) fetch(rb + 64);
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      accT acc = {0, 0, 0, 0};
 #pragma unroll
       for (int k4 = 0; k4 < NB / 4; ++k4) {
         const int a = 4 * k4 + lk;
-        acc = mfma16(Ws[a][16 * wv + li], Vs[16 * b + li][a], acc);
+        acc = Mfma<T>::mma(Ws[a][16 * wv + li], Vs[16 * b + li][a], acc);
       }
       const int r = rb + 16 * b + li;
       if (r < r1)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          if (col + v < nc) A[r + (int64_t)(c0 + col + v) * lda] = cc[b][v] - acc[v];
+          if (col[v] < nc) A[r + (int64_t)(c0 + col[v]) * lda] = cc[b][v] - acc[v];
     }
   }
 }
@@ -1088,13 +1110,17 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork&
     SPAQR_HIP(hipGetLastError());
     if (tiles > 0) {
       const dim3 g3(nf, tiles, segs), g2(nf, tiles);
-      if (sizeof(T) == 4)
-        hipLaunchKernelGGL(k_qru_w_mfma, g3, dim3(BS), 0, s, d_desc, j0, ws);
+      // SPAQR_VALU_UPDATE=1 keeps FP64 fronts on the vector-ALU update
+      // (for comparisons with the matrix-core form)
+      static const bool valu64 = std::getenv("SPAQR_VALU_UPDATE") != nullptr;
+      const bool mfma = sizeof(T) == 4 || !valu64;
+      if (mfma)
+        hipLaunchKernelGGL(k_qru_w_mfma<T>, g3, dim3(BS), 0, s, d_desc, j0, ws);
       else
         hipLaunchKernelGGL(k_qru_w<T>, g3, dim3(BS), 0, s, d_desc, j0, ws);
       hipLaunchKernelGGL(k_qru_reduce<T>, g2, dim3(BS), 0, s, d_desc, j0, ws);
-      if (sizeof(T) == 4)
-        hipLaunchKernelGGL(k_qru_apply_mfma, g3, dim3(BS), 0, s, d_desc, j0, ws);
+      if (mfma)
+        hipLaunchKernelGGL(k_qru_apply_mfma<T>, g3, dim3(BS), 0, s, d_desc, j0, ws);
       else
         hipLaunchKernelGGL(k_qru_apply<T>, g3, dim3(BS), 0, s, d_desc, j0, ws);
       SPAQR_HIP(hipGetLastError());
