@@ -110,7 +110,7 @@ typedef struct {
 
 /* Launch shapes of the factorization (see spaqr_autotune). */
 typedef struct {
-  int32_t pqr_poll;        /* pivot steps between host polls of a rank-revealing-QR batch (default 16) */
+  int32_t pqr_poll;        /* pivot steps launched ahead of the last one the GPU has reported (16)    */
   int32_t pqr_reg_rows;    /* tallest row window a pivot step keeps in registers, 0..1024 (1024)      */
   int32_t tall_coop;       /* 1: tall FP32 panels in one cooperative launch; 0: two per column (1)   */
   int32_t from_cache;      /* spaqr_autotune: 1 if the choice was read from the cache file           */

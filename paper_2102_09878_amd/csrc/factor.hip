@@ -121,6 +121,8 @@ void Handle::release_device() {
   d_pqr_err = nullptr;
   if (h_sc) (void)hipHostFree(h_sc);
   if (h_act) (void)hipHostFree(h_act);
+  if (h_pqr_report) (void)hipHostFree(h_pqr_report);
+  h_pqr_report = d_pqr_report = nullptr;
   d_segc = d_segr = nullptr;
   d_act = nullptr;
   h_act = nullptr;
@@ -171,6 +173,9 @@ void Handle::ensure_device() {
   d_pqr_err = dcopy(std::vector<int>(1), plan_bytes);
   SPAQR_HIP(hipHostMalloc((void**)&h_sc, (P.count * 8 + 64) * sizeof(double), hipHostMallocDefault));
   SPAQR_HIP(hipHostMalloc((void**)&h_act, P.count * sizeof(int), hipHostMallocDefault));
+  SPAQR_HIP(hipHostMalloc((void**)&h_pqr_report, 64, hipHostMallocCoherent | hipHostMallocMapped));
+  *h_pqr_report = 0;
+  SPAQR_HIP(hipHostGetDevicePointer((void**)&d_pqr_report, h_pqr_report, 0));
   dev_ready = true;
   scale_values(*this);
 }
@@ -298,6 +303,7 @@ class Factorizer {
     ++syncs_;
   }
   double wait_s_ = 0.0;
+  int report_fallbacks_ = 0;  // pivot-step loops that fell back to a stream read
 
   int next_forced() {
     if (!forced_) return -1;
@@ -546,20 +552,54 @@ class Factorizer {
     int steps = 0;
     timed_steps_.clear();
     pqr_launched_ = 0;
+    // Steps are launched ahead of the GPU, at most pqr_poll beyond the last
+    // step whose kernel has reported the live-matrix count (the report word
+    // in pinned host memory, tagged with this batch), so the stream never
+    // drains; once a report shows no live matrix, the steps already queued
+    // find every matrix stopped and only carry the state over.  Should the
+    // report not advance for a long time (more than 20 ms), the count is
+    // read through the stream instead.
+    const unsigned tag = (++H.pqr_tag) & 0xFFFFFFu;
+    volatile unsigned long long* rep = H.h_pqr_report;
+    int reported = -1;  // last step whose kernel has reported
     while (steps < kmax) {
       ++pqr_launched_;
       const bool timed = H.kt.pick("pqr_step");
       unsigned long long* stamp = timed ? H.kt.stamp(st) : nullptr;
       if (timed) timed_steps_.push_back(steps);
       launch_pqr_step<T>(dblk, total, total, states, parts, frop, dmap, active, steps, eps_, max_m, cw,
-                         H.tune.pqr_reg_rows, stamp, st);
+                         H.tune.pqr_reg_rows, stamp, H.d_pqr_report, tag, st);
       ++launches_;
       ++steps;
-      if (steps % H.tune.pqr_poll == 0 && steps < kmax) {
-        SPAQR_HIP(hipMemcpyAsync(h_active, active, sizeof(int), hipMemcpyDeviceToHost, st));
-        sync();
-        if (*h_active == 0) break;
+      if (steps >= kmax) break;
+      bool done = false;
+      double t_wait = -1.0;
+      const double t_spin = now_s();
+      for (;;) {
+        const unsigned long long w = *rep;
+        if ((unsigned)(w >> 40) == tag) {
+          const int s = (int)((w >> 20) & 0xFFFFFu);
+          if ((w & 0xFFFFFu) == 0) {
+            done = true;
+            break;
+          }
+          if (s > reported) reported = s, t_wait = -1.0;
+        }
+        if (steps - 1 - reported < H.tune.pqr_poll) break;
+        const double t = now_s();
+        if (t_wait < 0.0) {
+          t_wait = t;
+        } else if (t - t_wait > 0.02) {
+          SPAQR_HIP(hipMemcpyAsync(h_active, active, sizeof(int), hipMemcpyDeviceToHost, st));
+          sync();
+          ++report_fallbacks_;
+          done = *h_active == 0;
+          reported = steps - 1;
+          break;
+        }
       }
+      wait_s_ += now_s() - t_spin;
+      if (done) break;
     }
     launch_pqr_finish<T>(d, (int)q.size(), states, steps, st);
     ++launches_;

@@ -151,7 +151,7 @@ struct KernelTimer {
 
 // Launch shapes chosen per problem by spaqr_autotune (defaults otherwise).
 struct TuneParams {
-  int pqr_poll = 16;        // pivot steps between host polls of the live-matrix count
+  int pqr_poll = 16;        // pivot steps launched ahead of the last step the GPU has reported
   int pqr_reg_rows = 1024;  // tallest 64-aligned window kept in registers by a pivot step
   int tall_coop = 1;        // tall FP32 panels in one cooperative launch (else two launches per column)
 };
@@ -213,6 +213,11 @@ struct Handle {
   size_t cg_elems = 0;
   double* h_sc = nullptr;  // pinned scalars (count * 8 + 64 doubles)
   int* h_act = nullptr;    // pinned flags (count ints)
+  // progress word of the pivot-step loop: written by the step kernels
+  // (coherent pinned host memory), read by the host without synchronising
+  unsigned long long* h_pqr_report = nullptr;
+  unsigned long long* d_pqr_report = nullptr;
+  unsigned pqr_tag = 0;
 
   ~Handle();
   void ensure_device();

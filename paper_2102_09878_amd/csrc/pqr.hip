@@ -167,8 +167,18 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
                                                  PQRPart* __restrict__ parts, int total_parts,
                                                  const double* __restrict__ frop,
                                                  const int2* __restrict__ bmap, int* __restrict__ active,
-                                                 int i, double eps, unsigned long long* stamp) {
+                                                 int i, double eps, unsigned long long* stamp,
+                                                 unsigned long long* report, unsigned tag) {
   const StampScope timing(stamp);
+  // progress for the host, which then needs no stream synchronisation to
+  // stop launching steps: the matrices still running after step i - 1
+  // (final at this kernel's start), tagged with the batch and the step
+  if (report && blockIdx.x == 0 && threadIdx.x == 0) {
+    const int a = __hip_atomic_load(active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long w = ((unsigned long long)(tag & 0xFFFFFFu) << 40) |
+                                 ((unsigned long long)(unsigned)i << 20) | (unsigned)min(max(a, 0), 0xFFFFF);
+    __hip_atomic_store(report, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
   extern __shared__ double x[];  // pivot column rows i..m-1
   __shared__ double sh[4];
   __shared__ double shv[4];
@@ -870,15 +880,17 @@ void launch_pqr_init(const PQRDesc* d_desc, int nblocks, PQRState* states, PQRPa
 template <typename T>
 void launch_pqr_step(const PQRDesc* d_blk, int nblocks, int total_parts, PQRState* states,
                      PQRPart* parts, const double* frop, const int2* bmap, int* active, int i, double eps,
-                     int max_m, int cw, int reg_rows, unsigned long long* stamp, hipStream_t s) {
+                     int max_m, int cw, int reg_rows, unsigned long long* stamp, unsigned long long* report,
+                     unsigned tag, hipStream_t s) {
   if (nblocks <= 0) return;
+  if (i >= (1 << 20)) throw Error(SPAQR_EARG, "internal: pivot step index beyond the progress word");
   const size_t lds = (size_t)std::max(1, max_m) * sizeof(double);
   if (lds > 64 * 1024) throw Error(SPAQR_EARG, "rank-revealing QR block taller than 8192 rows");
   const int rows = max_m - (i & ~63);
   const bool regs = rows <= std::min(reg_rows, 1024);
 #define SPAQR_PQR_GO(Q, C)                                                                                   \
   hipLaunchKernelGGL((k_pqr_step<T, Q, C>), dim3(nblocks), dim3(BS), lds, s, d_blk, states, parts, total_parts,  \
-                     frop, bmap, active, i, eps, stamp)
+                     frop, bmap, active, i, eps, stamp, report, tag)
   if (cw == PQR_CW) {
     if (!regs)
       SPAQR_PQR_GO(0, PQR_CW / 4);
@@ -1006,7 +1018,8 @@ void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int st
 #define SPAQR_PQR_INST(T)                                                                             \
   template void launch_pqr_init<T>(const PQRDesc*, int, PQRState*, PQRPart*, double*, const int2*, hipStream_t); \
   template void launch_pqr_step<T>(const PQRDesc*, int, int, PQRState*, PQRPart*, const double*, const int2*,  \
-                                   int*, int, double, int, int, int, unsigned long long*, hipStream_t);         \
+                                   int*, int, double, int, int, int, unsigned long long*,                     \
+                                   unsigned long long*, unsigned, hipStream_t);                               \
   template void launch_pqr_finish<T>(const PQRDesc*, int, PQRState*, int, hipStream_t);                   \
   template int pqr_run_width<T>(int, const std::vector<int>&, int*);                                     \
   template void launch_pqr_run<T>(const PQRDesc*, int, const int2*, const PQRXch&, double, int,            \

@@ -2,9 +2,10 @@
 //
 // Three knobs change how the same arithmetic is launched, never what is
 // computed beyond rounding of the panel form:
-//   * pqr_poll      pivot steps of a rank-revealing-QR batch between host
-//                   polls of its live-matrix count (fewer polls, more empty
-//                   launches once every matrix has stopped);
+//   * pqr_poll      pivot steps of a rank-revealing-QR batch launched ahead
+//                   of the last step the GPU has reported its live-matrix
+//                   count for (a deeper queue, more empty launches once every
+//                   matrix has stopped);
 //   * pqr_reg_rows  tallest 64-aligned row window a pivot step keeps in
 //                   registers (per-lane register tile of 2 to 16 rows, or
 //                   the memory path above it; both sum in the same order);
@@ -111,7 +112,7 @@ void autotune(Handle& H, double eps, int reps, const char* cache_path, spaqr_tun
       ++evals;
       if (t < t_best) t_best = t, best = c;
     };
-    for (int poll : {4, 64}) {
+    for (int poll : {4, 8}) {
       TuneParams c = best;
       c.pqr_poll = poll;
       consider(c);
