@@ -274,16 +274,49 @@ class Factorizer {
   };
 
   std::vector<int> colmap(const RG& g, const std::vector<int>& cols, bool required) {
-    for (size_t i = 0; i < g.slots.size(); ++i) pos[g.slots[i]] = (int)i;
+    index_slots(g.slots);
     std::vector<int> m(cols.size());
-    bool ok = true;
-    for (size_t c = 0; c < cols.size(); ++c) {
-      m[c] = pos[cols[c]];
-      ok = ok && m[c] >= 0;
-    }
-    for (int s : g.slots) pos[s] = -1;
+    const bool ok = lookup(cols, m.data());
+    clear_slots(g.slots);
     if (required && !ok) throw Error(SPAQR_EARG, "internal: group lacks a column of a touched cluster");
     return m;
+  }
+  // pos[s] = position of slot s in `slots` (until clear_slots)
+  void index_slots(const std::vector<int>& slots) {
+    for (size_t i = 0; i < slots.size(); ++i) pos[slots[i]] = (int)i;
+  }
+  void clear_slots(const std::vector<int>& slots) {
+    for (int v : slots) pos[v] = -1;
+  }
+  // out[c] = pos[cols[c]]; false if a slot of cols is not indexed
+  bool lookup(const std::vector<int>& cols, int* out) const {
+    bool ok = true;
+    for (size_t c = 0; c < cols.size(); ++c) {
+      out[c] = pos[cols[c]];
+      ok = ok && out[c] >= 0;
+    }
+    return ok;
+  }
+  // Appends to the pool the column map of group g into a front whose
+  // columns are indexed in pos (index_slots of the front's columns): entry c
+  // is g's column holding front column c, -1 where g has none; the same map
+  // as colmap(g, front columns, false), built from g's side.
+  size_t front_map(IntPool& pool, const RG& g, int n) {
+    const size_t o = pool.v.size();
+    pool.v.resize(o + n, -1);
+    int* m = pool.v.data() + o;
+    for (size_t i = 0; i < g.slots.size(); ++i) {
+      const int c = pos[g.slots[i]];
+      if (c >= 0) m[c] = (int)i;
+    }
+    return o;
+  }
+  // Appends the required map of `cols` into the indexed slot list.
+  size_t subset_map(IntPool& pool, const std::vector<int>& cols) {
+    const size_t o = pool.v.size();
+    pool.v.resize(o + cols.size());
+    if (!lookup(cols, pool.v.data() + o)) throw Error(SPAQR_EARG, "internal: group lacks a column of a touched cluster");
+    return o;
   }
 
   std::vector<int> slots_of(const std::vector<int>& clus) {
@@ -790,6 +823,7 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
     f.ld = pad(f.m);
     f.F = talloc(f.ld * f.n);
     int64_t row0 = 0;
+    index_slots(f.cols);
     for (int pass = 0; pass < 2; ++pass)
       for (int g : pass == 0 ? f.owned : f.foreign) {
         GatherDesc d{};
@@ -802,10 +836,11 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
         d.nrows = G[g].nrows;
         d.ncols = f.n;
         d.transpose = 0;
-        gd_map.push_back(pool.add(colmap(G[g], f.cols, false)));
+        gd_map.push_back(front_map(pool, G[g], f.n));
         gd.push_back(d);
         row0 += G[g].nrows;
       }
+    clear_slots(f.cols);
     maxc = std::max(maxc, f.n);
     QRDesc q{};
     q.A = f.F;
@@ -1010,6 +1045,7 @@ void Factorizer<T>::scale_all() {
     f.ld = pad(f.m);
     f.F = talloc(f.ld * f.n);
     int64_t row0 = 0;
+    index_slots(f.cols);
     for (int g : C[f.p].groups) {
       GatherDesc d{};
       d.src = G[g].data;
@@ -1019,10 +1055,11 @@ void Factorizer<T>::scale_all() {
       d.row0 = row0;
       d.nrows = G[g].nrows;
       d.ncols = f.n;
-      gd_map.push_back(pool.add(colmap(G[g], f.cols, false)));
+      gd_map.push_back(front_map(pool, G[g], f.n));
       gd.push_back(d);
       row0 += G[g].nrows;
     }
+    clear_slots(f.cols);
     maxc = std::max(maxc, f.n);
     QRDesc q{};
     q.A = f.F;
@@ -1096,6 +1133,7 @@ void Factorizer<T>::scale_all() {
   int td_rows = 0, td_c = 0;
   for (int g : live_groups()) {
     RG& gr = G[g];
+    index_slots(gr.slots);
     for (int q : gr.clus) {
       if (gr.role == 1 && gr.owner == q) continue;
       TrsmDesc d{};
@@ -1105,13 +1143,14 @@ void Factorizer<T>::scale_all() {
       d.ldr = (int64_t)C[q].slots.size();
       d.nrows = gr.nrows;
       d.c = (int)C[q].slots.size();
-      td_map.push_back(tp.add(colmap(gr, C[q].slots, true)));
+      td_map.push_back(subset_map(tp, C[q].slots));
       td.push_back(d);
       td_rows = std::max(td_rows, d.nrows);
       td_c = std::max(td_c, d.c);
       flops_[PH_SCALE] += (double)gr.nrows * d.c * d.c;
       bytes_[PH_SCALE] += 2.0 * sizeof(T) * gr.nrows * d.c;
     }
+    clear_slots(gr.slots);
   }
   int* dtp = upload(tp.v);
   for (size_t i = 0; i < td.size(); ++i) td[i].colmap = dtp + td_map[i];
@@ -1266,7 +1305,10 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
       col0 += G[g].nrows;
     }
     {
-      const size_t o = pool.add(colmap(G[s.p1], s.oslots, true));
+      index_slots(G[s.p1].slots);
+      const size_t o = subset_map(pool, s.oslots);
+      const size_t oi = subset_map(pool, s.pslots);
+      clear_slots(G[s.p1].slots);
       GatherDesc d{};
       d.src = G[s.p1].data;
       d.dst = s.Cb;
@@ -1289,7 +1331,6 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
       w.ncols = (int)s.oslots.size();
       sd_map.push_back(o);
       sd.push_back(w);
-      const size_t oi = pool.add(colmap(G[s.p1], s.pslots, true));
       ScatterDesc idw{};
       idw.dst = G[s.p1].data;
       idw.rank = d_rank + i;
@@ -1372,14 +1413,15 @@ void Factorizer<T>::reassign_group_rows(int gi) {
   RG src = G[gi];
   kill_group(gi);
   if (src.clus.empty() || src.nrows == 0) return;
-  std::vector<int> cm, off{0};
-  for (int c : src.clus) {
-    std::vector<int> m = colmap(src, C[c].slots, true);
-    cm.insert(cm.end(), m.begin(), m.end());
-    off.push_back((int)cm.size());
-  }
+  std::vector<int> off{0};
   IntPool pool;
-  const size_t ocm = pool.add(cm), oof = pool.add(off);
+  index_slots(src.slots);
+  for (int c : src.clus) {
+    subset_map(pool, C[c].slots);
+    off.push_back((int)pool.v.size());
+  }
+  clear_slots(src.slots);
+  const size_t ocm = 0, oof = pool.add(off);
   int* dp = upload(pool.v);
   int* d_owner = static_cast<int*>(H.arena.alloc(src.nrows * sizeof(int)));
   OwnerDesc d{};
