@@ -297,19 +297,44 @@ class Factorizer {
     }
     return ok;
   }
-  // Appends to the pool the column map of group g into a front whose
-  // columns are indexed in pos (index_slots of the front's columns): entry c
-  // is g's column holding front column c, -1 where g has none; the same map
-  // as colmap(g, front columns, false), built from g's side.
-  size_t front_map(IntPool& pool, const RG& g, int n) {
-    const size_t o = pool.v.size();
-    pool.v.resize(o + n, -1);
-    int* m = pool.v.data() + o;
-    for (size_t i = 0; i < g.slots.size(); ++i) {
-      const int c = pos[g.slots[i]];
-      if (c >= 0) m[c] = (int)i;
-    }
+  // Column maps of front gathers, expanded on the device: the host lists
+  // the front column of each of a group's slots, k_expand_maps turns the
+  // list into the gather's map (entry c: g's column holding front column c,
+  // -1 where g has none; the map colmap(g, front columns, false) gives).
+  struct FrontMaps {
+    IntPool fpos;
+    std::vector<ExpandDesc> xd;
+    std::vector<size_t> fo;
+    int64_t dense = 0;
+  };
+  // Records the map of group g into a front of n columns indexed in pos
+  // (index_slots of the front's columns); returns its offset in the
+  // expanded maps.
+  size_t front_map(FrontMaps& fm, const RG& g, int n) {
+    ExpandDesc e{};
+    e.nslots = (int)g.slots.size();
+    e.n = n;
+    fm.fo.push_back(fm.fpos.v.size());
+    for (int sl : g.slots) fm.fpos.v.push_back(pos[sl]);
+    fm.xd.push_back(e);
+    const size_t o = (size_t)fm.dense;
+    fm.dense += n;
     return o;
+  }
+  // Uploads the lists and expands them on the device (in stream order
+  // before the gather); returns the expanded maps.
+  int* expand(FrontMaps& fm) {
+    int* dense = static_cast<int*>(H.arena.alloc(std::max<int64_t>(1, fm.dense) * sizeof(int)));
+    int* dp = upload(fm.fpos.v);
+    size_t off = 0;
+    for (size_t k = 0; k < fm.xd.size(); ++k) {
+      fm.xd[k].fpos = dp ? dp + fm.fo[k] : nullptr;
+      fm.xd[k].out = dense + off;
+      off += fm.xd[k].n;
+    }
+    launch_expand_maps(upload(fm.xd), (int)fm.xd.size(), st);
+    ++launches_;
+    return dense;
   }
   // Appends the required map of `cols` into the indexed slot list.
   size_t subset_map(IntPool& pool, const std::vector<int>& cols) {
@@ -782,7 +807,7 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
     int64_t ld;
   };
   std::vector<Front> fr(sel.size());
-  IntPool pool;
+  FrontMaps fm;
   std::vector<GatherDesc> gd;
   std::vector<size_t> gd_map;
   std::vector<QRDesc> qd;
@@ -836,7 +861,7 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
         d.nrows = G[g].nrows;
         d.ncols = f.n;
         d.transpose = 0;
-        gd_map.push_back(front_map(pool, G[g], f.n));
+        gd_map.push_back(front_map(fm, G[g], f.n));
         gd.push_back(d);
         row0 += G[g].nrows;
       }
@@ -853,8 +878,8 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
     flops_[PH_ELIM] += qr_flops(f.m, f.cs) + 4.0 * f.m * f.cs * f.cN - 2.0 * f.cs * f.cs * f.cN;
     bytes_[PH_ELIM] += 2.0 * sizeof(T) * f.m * f.n;
   }
-  int* dpool = upload(pool.v);
-  for (size_t i = 0; i < gd.size(); ++i) gd[i].colmap = dpool + gd_map[i];
+  int* dmaps = expand(fm);
+  for (size_t i = 0; i < gd.size(); ++i) gd[i].colmap = dmaps + gd_map[i];
   launch_gather<T>(upload(gd), (int)gd.size(), maxc, st);
   ++launches_;
   for (auto& f : fr) dump_front("elim", f.s, f.F, f.ld, f.m, f.n, f.cols);
@@ -1008,7 +1033,7 @@ template <typename T>
 void Factorizer<T>::scale_all() {
   timer_begin(PH_SCALE);
   std::vector<int> ifaces(live.begin(), live.end());
-  IntPool pool;
+  FrontMaps fm;
   std::vector<GatherDesc> gd;
   std::vector<size_t> gd_map;
   std::vector<QRDesc> qd;
@@ -1055,7 +1080,7 @@ void Factorizer<T>::scale_all() {
       d.row0 = row0;
       d.nrows = G[g].nrows;
       d.ncols = f.n;
-      gd_map.push_back(front_map(pool, G[g], f.n));
+      gd_map.push_back(front_map(fm, G[g], f.n));
       gd.push_back(d);
       row0 += G[g].nrows;
     }
@@ -1088,8 +1113,8 @@ void Factorizer<T>::scale_all() {
     bytes_[PH_SCALE] += 2.0 * sizeof(T) * f.m * f.n;
     sf.push_back(std::move(f));
   }
-  int* dpool = upload(pool.v);
-  for (size_t i = 0; i < gd.size(); ++i) gd[i].colmap = dpool + gd_map[i];
+  int* dmaps = expand(fm);
+  for (size_t i = 0; i < gd.size(); ++i) gd[i].colmap = dmaps + gd_map[i];
   launch_gather<T>(upload(gd), (int)gd.size(), maxc, st);
   ++launches_;
   for (auto& f : sf) dump_front("scale", f.p, f.F, f.ld, f.m, f.n, f.cols);

@@ -81,6 +81,17 @@ __global__ __launch_bounds__(BS) void k_gather(const GatherDesc* __restrict__ D)
   }
 }
 
+// one work-group per map: clear, then place the group's columns
+__global__ __launch_bounds__(BS) void k_expand_maps(const ExpandDesc* __restrict__ D) {
+  const ExpandDesc d = D[blockIdx.x];
+  for (int c = threadIdx.x; c < d.n; c += BS) d.out[c] = -1;
+  __syncthreads();
+  for (int i = threadIdx.x; i < d.nslots; i += BS) {
+    const int c = d.fpos[i];
+    if (c >= 0 && c < d.n) d.out[c] = i;
+  }
+}
+
 template <typename T>
 __global__ void k_scatter_csr(T* __restrict__ base, const int64_t* __restrict__ dst,
                               const double* __restrict__ val, int64_t nnz) {
@@ -318,6 +329,12 @@ void launch_gather(const GatherDesc* d_desc, int n, int max_cols, hipStream_t s)
   if (n <= 0 || max_cols <= 0) return;
   dim3 grid(n, (max_cols + GATHER_COLS - 1) / GATHER_COLS);
   hipLaunchKernelGGL(k_gather<T>, grid, dim3(BS), 0, s, d_desc);
+  SPAQR_HIP(hipGetLastError());
+}
+
+void launch_expand_maps(const ExpandDesc* d_desc, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_expand_maps, dim3(n), dim3(BS), 0, s, d_desc);
   SPAQR_HIP(hipGetLastError());
 }
 

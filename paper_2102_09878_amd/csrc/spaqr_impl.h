@@ -167,6 +167,15 @@ struct GatherDesc {
   int nrows, ncols, transpose, pad_;
 };
 
+// Column map of a gather built on the device from the group's side: out[c]
+// = i where fpos[i] = c (fpos: front column of each of the group's nslots
+// columns, -1 where the front has none), -1 for the other c < n.
+struct ExpandDesc {
+  const int* fpos;
+  int* out;
+  int nslots, n;
+};
+
 // Householder QR of the leading k columns of A (m x n, ld lda); the
 // reflectors are applied to all n columns.  tau[min(m,k)].
 struct QRDesc {
@@ -299,6 +308,7 @@ constexpr int APPLY_CHUNK = 256;
 
 template <typename T>
 void launch_gather(const GatherDesc* d_desc, int n, int max_cols, hipStream_t s);
+void launch_expand_maps(const ExpandDesc* d_desc, int n, hipStream_t s);
 template <typename T>
 void launch_scatter_csr(T* base, const int64_t* dst, const double* ahat, int64_t nnz, hipStream_t s);
 // Blocked Householder QR of a batch.  Panels of QR_NB columns; a tall panel
