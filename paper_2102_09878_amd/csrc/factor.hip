@@ -394,6 +394,60 @@ class Factorizer {
       for (int g : C[c].groups) out.push_back(g);
     return out;
   }
+  // Owner and position in the owner's list of every live group (valid while
+  // lgen_[g] == gen_, until the structure changes): the order in which a
+  // scan of live_groups() meets them is (owner, position).
+  std::vector<int> lgen_, lown_, lpos_;
+  int gen_ = 0;
+  std::vector<int> cstamp_;  // per cluster: set to cgen_ once listed
+  int cgen_ = 0;
+  void index_live_groups() {
+    if (lgen_.size() < G.size()) {
+      lgen_.resize(G.size(), 0);
+      lown_.resize(G.size(), -1);
+      lpos_.resize(G.size(), -1);
+    }
+    ++gen_;
+    for (int c : live)
+      for (size_t k = 0; k < C[c].groups.size(); ++k) {
+        const int g = C[c].groups[k];
+        lgen_[g] = gen_;
+        lown_[g] = c;
+        lpos_[g] = (int)k;
+      }
+  }
+  bool is_live(int g) const { return g < (int)lgen_.size() && lgen_[g] == gen_; }
+  bool holds(int g, int s) const {
+    const auto& cl = G[g].clus;
+    return std::find(cl.begin(), cl.end(), s) != cl.end();
+  }
+  // Drops from touch[s] the groups that are dead or no longer hold s, and
+  // repeated entries, once the list has doubled since it was last compacted.
+  std::vector<int> tsize_;
+  void compact_touch(int s) {
+    auto& t = touch[s];
+    if (tsize_.size() < touch.size()) tsize_.resize(touch.size(), 0);
+    if (t.size() <= 2 * (size_t)tsize_[s] + 16) return;
+    std::sort(t.begin(), t.end());
+    t.erase(std::unique(t.begin(), t.end()), t.end());
+    t.erase(std::remove_if(t.begin(), t.end(), [&](int g) { return !G[g].alive || !holds(g, s); }), t.end());
+    tsize_[s] = (int)t.size();
+  }
+  // live groups whose cluster list holds s (touch[s] filtered), in the
+  // order of a scan of live_groups(); owned by s too unless skip_own
+  std::vector<int> holders(int s, bool skip_own) {
+    compact_touch(s);
+    std::vector<int> h;
+    for (int g : touch[s]) {
+      if (!is_live(g) || (skip_own && lown_[g] == s)) continue;
+      if (holds(g, s)) h.push_back(g);
+    }
+    std::sort(h.begin(), h.end(), [&](int a, int b) {
+      return lown_[a] != lown_[b] ? lown_[a] < lown_[b] : lpos_[a] < lpos_[b];
+    });
+    h.erase(std::unique(h.begin(), h.end()), h.end());
+    return h;
+  }
 
   void record_op(int kind, int phase, const void* R, const void* tau, int64_t ld, int n1, int n2,
                  const std::vector<int>& s1, const std::vector<int>& s2) {
@@ -748,27 +802,28 @@ void Factorizer<T>::eliminate_level(int m) {
     H.stats.top_cols = (int)C[s].slots.size();
     H.stats.top_rows = rows;
   }
-  std::vector<int> idx(P.clusters.size(), -1), mark(P.clusters.size(), 0);
+  std::vector<int> mark(P.clusters.size(), 0);
+  if (cstamp_.size() < P.clusters.size()) cstamp_.assign(P.clusters.size(), 0);
   while (!pending.empty()) {
     // neighbours of every pending cluster from the current structure: the
     // clusters touched by any live group that s owns or that touches s
-    for (size_t i = 0; i < pending.size(); ++i) idx[pending[i]] = (int)i;
+    // (the groups s owns, and the live groups of other owners that hold s)
+    // (each cluster once, s excluded; the order does not matter below)
+    index_live_groups();
     std::vector<std::vector<int>> nb(pending.size());
-    for (int c : live)
-      for (int g : C[c].groups) {
-        const RG& gr = G[g];
-        auto add = [&](int s) {
-          if (idx[s] >= 0) nb[idx[s]].insert(nb[idx[s]].end(), gr.clus.begin(), gr.clus.end());
-        };
-        add(c);
-        for (int q : gr.clus)
-          if (q != c) add(q);
-      }
     for (size_t i = 0; i < pending.size(); ++i) {
+      const int s = pending[i];
       auto& u = nb[i];
-      std::sort(u.begin(), u.end());
-      u.erase(std::unique(u.begin(), u.end()), u.end());
-      u.erase(std::remove(u.begin(), u.end(), pending[i]), u.end());
+      ++cgen_;
+      cstamp_[s] = cgen_;
+      auto add = [&](int g) {
+        for (int q : G[g].clus)
+          if (cstamp_[q] != cgen_) cstamp_[q] = cgen_, u.push_back(q);
+      };
+      for (int g : C[s].groups) add(g);
+      compact_touch(s);
+      for (int g : touch[s])
+        if (is_live(g) && lown_[g] != s && holds(g, s)) add(g);
     }
     // greedy round in id order: s joins unless a cluster already taken is
     // its neighbour or has it as a neighbour (mark[] holds both relations)
@@ -787,7 +842,6 @@ void Factorizer<T>::eliminate_level(int m) {
       }
     }
     for (size_t i = 0; i < pending.size(); ++i) {
-      idx[pending[i]] = -1;
       mark[pending[i]] = 0;
       for (int q : nb[i]) mark[q] = 0;
     }
@@ -815,14 +869,8 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
   timer_begin(PH_ELIM);
   // foreign rows of every front in one pass over the live groups (by owner
   // id, then group order): groups of other owners that touch the front
-  {
-    std::vector<int> fidx(P.clusters.size(), -1);
-    for (size_t i = 0; i < sel.size(); ++i) fidx[sel[i]] = (int)i;
-    for (int c : live)
-      for (int g : C[c].groups)
-        for (int q : G[g].clus)
-          if (q != c && fidx[q] >= 0) fr[fidx[q]].foreign.push_back(g);
-  }
+  index_live_groups();
+  for (size_t i = 0; i < sel.size(); ++i) fr[i].foreign = holders(sel[i], true);
   for (size_t i = 0; i < sel.size(); ++i) {
     Front& f = fr[i];
     f.s = sel[i];
@@ -1281,9 +1329,10 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
         if (G[g].role == 1) ss[i].p1 = g;
       if (ss[i].p1 < 0) throw Error(SPAQR_EARG, "internal: interface without scaled rows");
     }
-    for (int g : live_groups())
-      for (int q : G[g].clus)
-        if (sidx[q] >= 0 && g != ss[sidx[q]].p1) ss[sidx[q]].blocks.push_back(g);
+    index_live_groups();
+    for (size_t i = 0; i < sel.size(); ++i)
+      for (int g : holders(sel[i], false))
+        if (g != ss[i].p1) ss[i].blocks.push_back(g);
   }
   for (size_t i = 0; i < sel.size(); ++i) {
     S2& s = ss[i];
