@@ -273,14 +273,6 @@ class Factorizer {
     }
   };
 
-  std::vector<int> colmap(const RG& g, const std::vector<int>& cols, bool required) {
-    index_slots(g.slots);
-    std::vector<int> m(cols.size());
-    const bool ok = lookup(cols, m.data());
-    clear_slots(g.slots);
-    if (required && !ok) throw Error(SPAQR_EARG, "internal: group lacks a column of a touched cluster");
-    return m;
-  }
   // pos[s] = position of slot s in `slots` (until clear_slots)
   void index_slots(const std::vector<int>& slots) {
     for (size_t i = 0; i < slots.size(); ++i) pos[slots[i]] = (int)i;
@@ -300,7 +292,7 @@ class Factorizer {
   // Column maps of front gathers, expanded on the device: the host lists
   // the front column of each of a group's slots, k_expand_maps turns the
   // list into the gather's map (entry c: g's column holding front column c,
-  // -1 where g has none; the map colmap(g, front columns, false) gives).
+  // -1 where g has none).
   struct FrontMaps {
     IntPool fpos;
     std::vector<ExpandDesc> xd;
@@ -335,6 +327,21 @@ class Factorizer {
     launch_expand_maps(upload(fm.xd), (int)fm.xd.size(), st);
     ++launches_;
     return dense;
+  }
+  // Appends the required map of an indexed column list (index_slots of a
+  // list of n columns) into group g's columns: entry k is g's column holding
+  // column k of the list, found in one pass over g's slots.
+  size_t subset_map_from(IntPool& pool, const RG& g, int n) {
+    const size_t o = pool.v.size();
+    pool.v.resize(o + n, -1);
+    int* m = pool.v.data() + o;
+    for (size_t i = 0; i < g.slots.size(); ++i) {
+      const int k = pos[g.slots[i]];
+      if (k >= 0) m[k] = (int)i;
+    }
+    for (int k = 0; k < n; ++k)
+      if (m[k] < 0) throw Error(SPAQR_EARG, "internal: group lacks a column of a touched cluster");
+    return o;
   }
   // Appends the required map of `cols` into the indexed slot list.
   size_t subset_map(IntPool& pool, const std::vector<int>& cols) {
@@ -437,15 +444,16 @@ class Factorizer {
   // order of a scan of live_groups(); owned by s too unless skip_own
   std::vector<int> holders(int s, bool skip_own) {
     compact_touch(s);
-    std::vector<int> h;
+    std::vector<std::pair<int64_t, int>> k;
     for (int g : touch[s]) {
       if (!is_live(g) || (skip_own && lown_[g] == s)) continue;
-      if (holds(g, s)) h.push_back(g);
+      if (holds(g, s)) k.emplace_back(((int64_t)lown_[g] << 32) | (uint32_t)lpos_[g], g);
     }
-    std::sort(h.begin(), h.end(), [&](int a, int b) {
-      return lown_[a] != lown_[b] ? lown_[a] < lown_[b] : lpos_[a] < lpos_[b];
-    });
-    h.erase(std::unique(h.begin(), h.end()), h.end());
+    std::sort(k.begin(), k.end());
+    std::vector<int> h;
+    h.reserve(k.size());
+    for (size_t i = 0; i < k.size(); ++i)
+      if (i == 0 || k[i].first != k[i - 1].first) h.push_back(k[i].second);
     return h;
   }
 
@@ -1349,9 +1357,9 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
     s.V = talloc((int64_t)s.cp * std::max(1, std::min(s.cp, s.K)));
     s.tau = talloc(std::max(1, std::min(s.cp, s.K)));
     int64_t col0 = 0;
+    index_slots(s.pslots);
     for (int g : s.blocks) {
-      const std::vector<int> cm = colmap(G[g], s.pslots, true);
-      const size_t o = pool.add(cm);
+      const size_t o = subset_map_from(pool, G[g], s.cp);
       GatherDesc d{};
       d.src = G[g].data;
       d.dst = s.Cb;
@@ -1378,6 +1386,7 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
       sd.push_back(w);
       col0 += G[g].nrows;
     }
+    clear_slots(s.pslots);
     {
       index_slots(G[s.p1].slots);
       const size_t o = subset_map(pool, s.oslots);
