@@ -23,7 +23,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <numeric>
+#include <unordered_map>
 
 #include "handle.h"
 
@@ -215,12 +217,19 @@ class Factorizer {
   void run();
 
  private:
+  typedef std::shared_ptr<const std::vector<int>> Slots;
   struct RG {
     int owner = -1;
     T* data = nullptr;
     int64_t ld = 0;
     int nrows = 0;
-    std::vector<int> slots;
+    // column slots of the data, shared by the groups made from one front
+    // (so a map into them is found once per list)
+    Slots sl;
+    const std::vector<int>& slots() const {
+      static const std::vector<int> none;
+      return sl ? *sl : none;
+    }
     std::vector<int> clus;  // sorted
     int role = 0;           // 1: scaled rows p1, 2: rows below them p2
     bool alive = true;
@@ -298,19 +307,24 @@ class Factorizer {
     std::vector<ExpandDesc> xd;
     std::vector<size_t> fo;
     int64_t dense = 0;
+    std::unordered_map<const std::vector<int>*, size_t> cache;  // this front's maps by slot list
   };
   // Records the map of group g into a front of n columns indexed in pos
   // (index_slots of the front's columns); returns its offset in the
   // expanded maps.
   size_t front_map(FrontMaps& fm, const RG& g, int n) {
+    // groups sharing a slot list share the map (within one front)
+    auto hit = fm.cache.find(g.sl.get());
+    if (hit != fm.cache.end()) return hit->second;
     ExpandDesc e{};
-    e.nslots = (int)g.slots.size();
+    e.nslots = (int)g.slots().size();
     e.n = n;
     fm.fo.push_back(fm.fpos.v.size());
-    for (int sl : g.slots) fm.fpos.v.push_back(pos[sl]);
+    for (int v : g.slots()) fm.fpos.v.push_back(pos[v]);
     fm.xd.push_back(e);
     const size_t o = (size_t)fm.dense;
     fm.dense += n;
+    fm.cache.emplace(g.sl.get(), o);
     return o;
   }
   // Uploads the lists and expands them on the device (in stream order
@@ -335,8 +349,9 @@ class Factorizer {
     const size_t o = pool.v.size();
     pool.v.resize(o + n, -1);
     int* m = pool.v.data() + o;
-    for (size_t i = 0; i < g.slots.size(); ++i) {
-      const int k = pos[g.slots[i]];
+    const std::vector<int>& gs = g.slots();
+    for (size_t i = 0; i < gs.size(); ++i) {
+      const int k = pos[gs[i]];
       if (k >= 0) m[k] = (int)i;
     }
     for (int k = 0; k < n; ++k)
@@ -783,7 +798,9 @@ void Factorizer<T>::init_groups() {
     g.data = base + ig.offset;
     g.ld = ig.ld;
     g.nrows = (int)ig.rows.size();
-    for (int c : ig.clus) g.slots.insert(g.slots.end(), P.clusters[c].cells.begin(), P.clusters[c].cells.end());
+    std::vector<int> sv;
+    for (int c : ig.clus) sv.insert(sv.end(), P.clusters[c].cells.begin(), P.clusters[c].cells.end());
+    g.sl = std::make_shared<const std::vector<int>>(std::move(sv));
     g.clus = ig.clus;
     C[ig.owner].groups.push_back((int)G.size());
     G.push_back(std::move(g));
@@ -864,6 +881,7 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
   struct Front {
     int s;
     std::vector<int> owned, foreign, nb, cols;
+    Slots s2;  // columns after the eliminated ones (shared by the groups left)
     int m, n, cs, cN, rs;
     T* F;
     int64_t ld;
@@ -905,6 +923,7 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
     f.F = talloc(f.ld * f.n);
     int64_t row0 = 0;
     index_slots(f.cols);
+    fm.cache.clear();
     for (int pass = 0; pass < 2; ++pass)
       for (int g : pass == 0 ? f.owned : f.foreign) {
         GatherDesc d{};
@@ -947,14 +966,15 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
   std::vector<size_t> ext;
   for (size_t i = 0; i < fr.size(); ++i) {
     Front& f = fr[i];
-    std::vector<int> s2(f.cols.begin() + f.cs, f.cols.end());
+    f.s2 = std::make_shared<const std::vector<int>>(f.cols.begin() + f.cs, f.cols.end());
+    const std::vector<int>& s2 = *f.s2;
     record_op(0, PH_ELIM, f.F, nullptr, f.ld, f.cs, f.cN, C[f.s].slots, s2);
     int64_t off = f.rs;
     for (int g : f.foreign) {
       RG& gr = G[g];
       gr.data = f.F + off + (int64_t)f.cs * f.ld;
       gr.ld = f.ld;
-      gr.slots = s2;
+      gr.sl = f.s2;
       gr.clus = f.nb;
       gr.role = 0;
       note(g);
@@ -1051,7 +1071,6 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
     bytes_[PH_REASSIGN] += sizeof(T) * (2 * m * n);
     std::vector<std::vector<int>> by(f.nb.size());
     for (int r = 0; r < k; ++r) by[h_owner[owner_base[e] + r]].push_back(r);
-    std::vector<int> s2(f.cols.begin() + f.cs, f.cols.end());
     for (size_t q = 0; q < f.nb.size(); ++q) {
       if (by[q].empty()) continue;
       RG g;
@@ -1059,7 +1078,7 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
       g.nrows = (int)by[q].size();
       g.ld = pad(g.nrows);
       g.data = talloc(g.ld * f.cN);
-      g.slots = s2;
+      g.sl = f.s2;
       g.clus = f.nb;
       RowCopyDesc d{};
       d.src = qe[e].A;
@@ -1127,6 +1146,7 @@ void Factorizer<T>::scale_all() {
     f.F = talloc(f.ld * f.n);
     int64_t row0 = 0;
     index_slots(f.cols);
+    fm.cache.clear();
     for (int g : C[f.p].groups) {
       GatherDesc d{};
       d.src = G[g].data;
@@ -1186,7 +1206,7 @@ void Factorizer<T>::scale_all() {
     p1.data = f.F;
     p1.ld = f.ld;
     p1.nrows = f.cs;
-    p1.slots = f.cols;
+    p1.sl = std::make_shared<const std::vector<int>>(f.cols);
     p1.clus = f.nb;
     p1.clus.insert(std::lower_bound(p1.clus.begin(), p1.clus.end(), f.p), f.p);
     p1.role = 1;
@@ -1199,7 +1219,7 @@ void Factorizer<T>::scale_all() {
       p2.data = f.F + f.cs + (int64_t)f.cs * f.ld;
       p2.ld = f.ld;
       p2.nrows = f.m - f.cs;
-      p2.slots.assign(f.cols.begin() + f.cs, f.cols.end());
+      p2.sl = std::make_shared<const std::vector<int>>(f.cols.begin() + f.cs, f.cols.end());
       p2.clus = f.nb;
       p2.role = 2;
       C[f.p].groups.push_back((int)G.size());
@@ -1214,7 +1234,7 @@ void Factorizer<T>::scale_all() {
   int td_rows = 0, td_c = 0;
   for (int g : live_groups()) {
     RG& gr = G[g];
-    index_slots(gr.slots);
+    index_slots(gr.slots());
     for (int q : gr.clus) {
       if (gr.role == 1 && gr.owner == q) continue;
       TrsmDesc d{};
@@ -1231,7 +1251,7 @@ void Factorizer<T>::scale_all() {
       flops_[PH_SCALE] += (double)gr.nrows * d.c * d.c;
       bytes_[PH_SCALE] += 2.0 * sizeof(T) * gr.nrows * d.c;
     }
-    clear_slots(gr.slots);
+    clear_slots(gr.slots());
   }
   int* dtp = upload(tp.v);
   for (size_t i = 0; i < td.size(); ++i) td[i].colmap = dtp + td_map[i];
@@ -1266,7 +1286,7 @@ void Factorizer<T>::step1_all() {
     RG& gr = G[who[i]];
     PQRDesc d{};
     d.A = gr.data;
-    d.n = (int)gr.slots.size();
+    d.n = (int)gr.slots().size();
     d.m = gr.nrows;
     d.lda = gr.ld;
     d.work = static_cast<double*>(H.arena.alloc(3 * std::max(1, d.n) * sizeof(double)));
@@ -1293,7 +1313,7 @@ void Factorizer<T>::step1_all() {
     RG& gr = G[who[i]];
     H.ranks.push_back(r);
     if (level_ > 0 && level_ < SPAQR_MAX_LEVELS) H.stats.level_rank1[level_] += r;
-    const double m = gr.nrows, n = (double)gr.slots.size();
+    const double m = gr.nrows, n = (double)gr.slots().size();
     flops_[PH_SPARSIFY] += 4 * m * n * r - 2.0 * r * r * (m + n) + 4.0 * r * r * r / 3 + 2 * m * n;
     bytes_[PH_SPARSIFY] += sizeof(T) * (2 * m * n);
     gr.nrows = r;
@@ -1358,8 +1378,11 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
     s.tau = talloc(std::max(1, std::min(s.cp, s.K)));
     int64_t col0 = 0;
     index_slots(s.pslots);
+    std::unordered_map<const std::vector<int>*, size_t> bcache;  // blocks sharing a slot list share the map
     for (int g : s.blocks) {
-      const size_t o = subset_map_from(pool, G[g], s.cp);
+      auto hit = bcache.find(G[g].sl.get());
+      const size_t o = hit != bcache.end() ? hit->second : subset_map_from(pool, G[g], s.cp);
+      bcache.emplace(G[g].sl.get(), o);
       GatherDesc d{};
       d.src = G[g].data;
       d.dst = s.Cb;
@@ -1388,10 +1411,10 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
     }
     clear_slots(s.pslots);
     {
-      index_slots(G[s.p1].slots);
+      index_slots(G[s.p1].slots());
       const size_t o = subset_map(pool, s.oslots);
       const size_t oi = subset_map(pool, s.pslots);
-      clear_slots(G[s.p1].slots);
+      clear_slots(G[s.p1].slots());
       GatherDesc d{};
       d.src = G[s.p1].data;
       d.dst = s.Cb;
@@ -1498,12 +1521,12 @@ void Factorizer<T>::reassign_group_rows(int gi) {
   if (src.clus.empty() || src.nrows == 0) return;
   std::vector<int> off{0};
   IntPool pool;
-  index_slots(src.slots);
+  index_slots(src.slots());
   for (int c : src.clus) {
     subset_map(pool, C[c].slots);
     off.push_back((int)pool.v.size());
   }
-  clear_slots(src.slots);
+  clear_slots(src.slots());
   const size_t ocm = 0, oof = pool.add(off);
   int* dp = upload(pool.v);
   int* d_owner = static_cast<int*>(H.arena.alloc(src.nrows * sizeof(int)));
@@ -1530,8 +1553,8 @@ void Factorizer<T>::reassign_group_rows(int gi) {
     g.owner = src.clus[q];
     g.nrows = (int)by[q].size();
     g.ld = pad(g.nrows);
-    g.data = talloc(g.ld * (int64_t)src.slots.size());
-    g.slots = src.slots;
+    g.data = talloc(g.ld * (int64_t)src.slots().size());
+    g.sl = src.sl;
     g.clus = src.clus;
     RowCopyDesc c{};
     c.src = src.data;
@@ -1539,7 +1562,7 @@ void Factorizer<T>::reassign_group_rows(int gi) {
     c.src_ld = src.ld;
     c.dst_ld = g.ld;
     c.nrows = g.nrows;
-    c.ncols = (int)src.slots.size();
+    c.ncols = (int)src.slots().size();
     rmap.push_back(rp.add(by[q]));
     rd.push_back(c);
     C[g.owner].groups.push_back((int)G.size());
@@ -1548,7 +1571,7 @@ void Factorizer<T>::reassign_group_rows(int gi) {
   }
   int* drp = upload(rp.v);
   for (size_t i = 0; i < rd.size(); ++i) rd[i].rows = drp + rmap[i];
-  launch_rowcopy<T>(upload(rd), (int)rd.size(), (int)src.slots.size(), st);
+  launch_rowcopy<T>(upload(rd), (int)rd.size(), (int)src.slots().size(), st);
   launches_ += 2;
 }
 
