@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -217,7 +218,34 @@ class Factorizer {
   void run();
 
  private:
-  typedef std::shared_ptr<const std::vector<int>> Slots;
+  // Column slots of a group's data: the slots of the clusters it was built
+  // from, one block after the other, with each block's (cluster, begin, end).
+  struct SlotList {
+    std::vector<int> v;
+    std::vector<std::array<int, 3>> blk;
+  };
+  typedef std::shared_ptr<const SlotList> Slots;
+  // the list `cols` made of the slot lists of `head` (if >= 0) then of the
+  // clusters `cl`, in that order (the blocks are cut by their sizes)
+  Slots make_slots(const std::vector<int>& cols, size_t from, int head, const std::vector<int>& cl) {
+    auto L = std::make_shared<SlotList>();
+    L->v.assign(cols.begin() + from, cols.end());
+    int at = 0;
+    auto block = [&](int c, int len) {
+      L->blk.push_back({c, at, at + len});
+      at += len;
+    };
+    if (head >= 0) block(head, (int)C[head].slots.size());
+    for (int q : cl) block(q, (int)C[q].slots.size());
+    if (at != (int)L->v.size()) throw Error(SPAQR_EARG, "internal: slot list blocks do not cover the list");
+    return L;
+  }
+  // c is p or one of the clusters merged into p
+  bool within(int c, int p) const {
+    for (; c >= 0; c = P.clusters[c].parent)
+      if (c == p) return true;
+    return false;
+  }
   struct RG {
     int owner = -1;
     T* data = nullptr;
@@ -228,7 +256,7 @@ class Factorizer {
     Slots sl;
     const std::vector<int>& slots() const {
       static const std::vector<int> none;
-      return sl ? *sl : none;
+      return sl ? sl->v : none;
     }
     std::vector<int> clus;  // sorted
     int role = 0;           // 1: scaled rows p1, 2: rows below them p2
@@ -307,7 +335,7 @@ class Factorizer {
     std::vector<ExpandDesc> xd;
     std::vector<size_t> fo;
     int64_t dense = 0;
-    std::unordered_map<const std::vector<int>*, size_t> cache;  // this front's maps by slot list
+    std::unordered_map<const SlotList*, size_t> cache;  // this front's maps by slot list
   };
   // Records the map of group g into a front of n columns indexed in pos
   // (index_slots of the front's columns); returns its offset in the
@@ -342,18 +370,29 @@ class Factorizer {
     ++launches_;
     return dense;
   }
-  // Appends the required map of an indexed column list (index_slots of a
-  // list of n columns) into group g's columns: entry k is g's column holding
-  // column k of the list, found in one pass over g's slots.
-  size_t subset_map_from(IntPool& pool, const RG& g, int n) {
+  // Appends the required map of an indexed column list (index_slots of the
+  // n columns of cluster p) into group g's columns: entry k is g's column
+  // holding column k of the list.
+  size_t subset_map_from(IntPool& pool, const RG& g, int n, int p) {
     const size_t o = pool.v.size();
     pool.v.resize(o + n, -1);
     int* m = pool.v.data() + o;
     const std::vector<int>& gs = g.slots();
-    for (size_t i = 0; i < gs.size(); ++i) {
-      const int k = pos[gs[i]];
-      if (k >= 0) m[k] = (int)i;
-    }
+    // first only the blocks of p and of the clusters merged into it (the
+    // list is cluster by cluster), then the whole list if that missed any
+    int found = 0;
+    if (g.sl)
+      for (const auto& b : g.sl->blk)
+        if (within(b[0], p))
+          for (int i = b[1]; i < b[2]; ++i) {
+            const int k = pos[gs[i]];
+            if (k >= 0 && m[k] < 0) m[k] = i, ++found;
+          }
+    if (found < n)
+      for (size_t i = 0; i < gs.size(); ++i) {
+        const int k = pos[gs[i]];
+        if (k >= 0) m[k] = (int)i;
+      }
     for (int k = 0; k < n; ++k)
       if (m[k] < 0) throw Error(SPAQR_EARG, "internal: group lacks a column of a touched cluster");
     return o;
@@ -798,9 +837,13 @@ void Factorizer<T>::init_groups() {
     g.data = base + ig.offset;
     g.ld = ig.ld;
     g.nrows = (int)ig.rows.size();
-    std::vector<int> sv;
-    for (int c : ig.clus) sv.insert(sv.end(), P.clusters[c].cells.begin(), P.clusters[c].cells.end());
-    g.sl = std::make_shared<const std::vector<int>>(std::move(sv));
+    auto L = std::make_shared<SlotList>();
+    for (int c : ig.clus) {
+      const auto& cells = P.clusters[c].cells;
+      L->blk.push_back({c, (int)L->v.size(), (int)(L->v.size() + cells.size())});
+      L->v.insert(L->v.end(), cells.begin(), cells.end());
+    }
+    g.sl = L;
     g.clus = ig.clus;
     C[ig.owner].groups.push_back((int)G.size());
     G.push_back(std::move(g));
@@ -966,8 +1009,8 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
   std::vector<size_t> ext;
   for (size_t i = 0; i < fr.size(); ++i) {
     Front& f = fr[i];
-    f.s2 = std::make_shared<const std::vector<int>>(f.cols.begin() + f.cs, f.cols.end());
-    const std::vector<int>& s2 = *f.s2;
+    f.s2 = make_slots(f.cols, f.cs, -1, f.nb);
+    const std::vector<int>& s2 = f.s2->v;
     record_op(0, PH_ELIM, f.F, nullptr, f.ld, f.cs, f.cN, C[f.s].slots, s2);
     int64_t off = f.rs;
     for (int g : f.foreign) {
@@ -1206,7 +1249,7 @@ void Factorizer<T>::scale_all() {
     p1.data = f.F;
     p1.ld = f.ld;
     p1.nrows = f.cs;
-    p1.sl = std::make_shared<const std::vector<int>>(f.cols);
+    p1.sl = make_slots(f.cols, 0, f.p, f.nb);
     p1.clus = f.nb;
     p1.clus.insert(std::lower_bound(p1.clus.begin(), p1.clus.end(), f.p), f.p);
     p1.role = 1;
@@ -1219,7 +1262,7 @@ void Factorizer<T>::scale_all() {
       p2.data = f.F + f.cs + (int64_t)f.cs * f.ld;
       p2.ld = f.ld;
       p2.nrows = f.m - f.cs;
-      p2.sl = std::make_shared<const std::vector<int>>(f.cols.begin() + f.cs, f.cols.end());
+      p2.sl = make_slots(f.cols, f.cs, -1, f.nb);
       p2.clus = f.nb;
       p2.role = 2;
       C[f.p].groups.push_back((int)G.size());
@@ -1378,10 +1421,10 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
     s.tau = talloc(std::max(1, std::min(s.cp, s.K)));
     int64_t col0 = 0;
     index_slots(s.pslots);
-    std::unordered_map<const std::vector<int>*, size_t> bcache;  // blocks sharing a slot list share the map
+    std::unordered_map<const SlotList*, size_t> bcache;  // blocks sharing a slot list share the map
     for (int g : s.blocks) {
       auto hit = bcache.find(G[g].sl.get());
-      const size_t o = hit != bcache.end() ? hit->second : subset_map_from(pool, G[g], s.cp);
+      const size_t o = hit != bcache.end() ? hit->second : subset_map_from(pool, G[g], s.cp, s.p);
       bcache.emplace(G[g].sl.get(), o);
       GatherDesc d{};
       d.src = G[g].data;
