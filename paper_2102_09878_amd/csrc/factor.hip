@@ -462,6 +462,19 @@ class Factorizer {
   int gen_ = 0;
   std::vector<int> cstamp_;  // per cluster: set to cgen_ once listed
   int cgen_ = 0;
+  // ascending clusters held by the groups of a and b, s excluded
+  std::vector<int> cluster_union(int s, const std::vector<int>& a, const std::vector<int>& b) {
+    if (cstamp_.size() < P.clusters.size()) cstamp_.assign(P.clusters.size(), 0);
+    ++cgen_;
+    cstamp_[s] = cgen_;
+    std::vector<int> u;
+    for (const auto* lst : {&a, &b})
+      for (int g : *lst)
+        for (int q : G[g].clus)
+          if (cstamp_[q] != cgen_) cstamp_[q] = cgen_, u.push_back(q);
+    std::sort(u.begin(), u.end());
+    return u;
+  }
   void index_live_groups() {
     if (lgen_.size() < G.size()) {
       lgen_.resize(G.size(), 0);
@@ -944,13 +957,7 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
     Front& f = fr[i];
     f.s = sel[i];
     f.owned = C[f.s].groups;
-    std::vector<int> u;
-    for (int g : f.owned) u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
-    for (int g : f.foreign) u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
-    std::sort(u.begin(), u.end());
-    u.erase(std::unique(u.begin(), u.end()), u.end());
-    u.erase(std::remove(u.begin(), u.end(), f.s), u.end());
-    f.nb = u;
+    f.nb = cluster_union(f.s, f.owned, f.foreign);
     f.cols = C[f.s].slots;
     std::vector<int> ns = slots_of(f.nb);
     f.cols.insert(f.cols.end(), ns.begin(), ns.end());
@@ -1171,12 +1178,7 @@ void Factorizer<T>::scale_all() {
   for (size_t i = 0; i < ifaces.size(); ++i) {
     SF f;
     f.p = ifaces[i];
-    std::vector<int> u;
-    for (int g : C[f.p].groups) u.insert(u.end(), G[g].clus.begin(), G[g].clus.end());
-    std::sort(u.begin(), u.end());
-    u.erase(std::unique(u.begin(), u.end()), u.end());
-    u.erase(std::remove(u.begin(), u.end(), f.p), u.end());
-    f.nb = u;
+    f.nb = cluster_union(f.p, C[f.p].groups, {});
     f.cols = C[f.p].slots;
     std::vector<int> ns = slots_of(f.nb);
     f.cols.insert(f.cols.end(), ns.begin(), ns.end());
