@@ -323,7 +323,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--forms", default="fp32,fp64")
     ap.add_argument("--family", default="pqr_step")
-    ap.add_argument("--every", type=int, default=1)
+    ap.add_argument("--every", type=int, default=128,
+                    help="launches of the roofline kernel per HIP-event-timed stretch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch form")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
@@ -385,7 +386,8 @@ def main() -> int:
         t1 = time.perf_counter()
         st = s.stats()
         kern = dict(calls=st["kernel_calls"], seconds=st["kernel_seconds"], bytes=st["kernel_bytes"],
-                    flops=st["kernel_flops"])
+                    flops=st["kernel_flops"], span_calls=st["kernel_span_calls"],
+                    span_seconds=st["kernel_span_seconds"])
         # outside the timed region: the one-shot seminormal solve refined to
         # the same stopping test (Section 1), on the last factor, beside CGLS
         torch.cuda.synchronize()
@@ -452,6 +454,10 @@ def main() -> int:
                     "traffic_over_algorithmic": traffic / per_launch if traffic else None,
                     "kernel": f"k_pqr_step<{'float' if best == 'fp32' else 'double'}>",
                     "avg_launch_us": kern["seconds"] / kern["calls"] * 1e6, "timed_launches": kern["calls"],
+                    "avg_launch_us_note": (f"every launch in the timed steps, between HIP events on the library's "
+                                           f"stream around stretches of {args.every} consecutive launches"),
+                    "in_kernel_span_us": (kern["span_seconds"] / kern["span_calls"] * 1e6
+                                          if kern["span_calls"] else None),
                     "algorithmic_flops_per_launch": kern["flops"] / kern["calls"],
                     "algorithmic_bytes_per_launch": per_launch,
                     "intensity_flop_per_byte": kern["flops"] / kern["bytes"] if kern["bytes"] else None,

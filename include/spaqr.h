@@ -106,6 +106,8 @@ typedef struct {
   int64_t level_rank1[SPAQR_MAX_LEVELS];      /* sum of step-1 ranks (rows kept)       */
   int64_t level_rank2[SPAQR_MAX_LEVELS];      /* sum of step-2 ranks (columns kept)    */
   double sync_wait_seconds;  /* host time spent waiting in those synchronisations   */
+  int64_t kernel_span_calls;   /* timed launches with in-kernel clock stamps          */
+  double kernel_span_seconds;  /* sum of their first-start to last-end spans         */
 } spaqr_stats;
 
 /* Launch shapes of the factorization (see spaqr_autotune). */
@@ -260,11 +262,17 @@ int spaqr_factor_stats(spaqr_handle h, spaqr_stats* out);
 /* Time every `every`-th launch (every >= 1) of one kernel family with HIP
  * events on the handle's stream and count the algorithmic bytes and flops
  * of the timed launches (exposed through spaqr_factor_stats); resets the
- * counters.  family: "pqr_step" (one pivot step of the batched
+ * counters.  For "pqr_step" every launch is timed instead, in stretches of
+ * `every` consecutive launches between two events (two event packets per
+ * stretch), so kernel_seconds / kernel_calls is the time per launch on the
+ * stream, dispatch included.  family: "pqr_step" (one pivot step of the batched
  * rank-revealing QRs: algorithmic flops and bytes of each batch, block read
  * and kept rows written once, shared over its step launches), "apply" (one
  * batch of W^-1 / W^-T ops) or "qrp_coop" (one cooperative tall Householder
  * panel of an elimination round), or NULL / "" to stop.  SPAQR_EARG for an unknown family or every < 1.
+ * The first "pqr_step" launch of each stretch also stamps its first
+ * work-group start and last work-group end with the GPU's constant-rate
+ * clock (kernel_span_*).
  * Measurement aid: each timed launch adds two event records. */
 int spaqr_time_kernel(spaqr_handle h, const char* family, int32_t every);
 

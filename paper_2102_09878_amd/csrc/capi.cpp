@@ -274,6 +274,8 @@ int spaqr_factor_stats(spaqr_handle h, spaqr_stats* out) {
     out->kernel_seconds = h->h.kt.seconds;
     out->kernel_bytes = h->h.kt.bytes;
     out->kernel_flops = h->h.kt.flops;
+    out->kernel_span_calls = h->h.kt.span_calls;
+    out->kernel_span_seconds = h->h.kt.span_seconds;
     return SPAQR_OK;
   });
 }

@@ -747,15 +747,31 @@ class Factorizer {
     // report not advance for a long time (more than 20 ms), the count is
     // read through the stream instead.
     const unsigned tag = (++H.pqr_tag) & 0xFFFFFFu;
+    int run_left = 0, run_len = 0;  // timed stretch in progress
     volatile unsigned long long* rep = H.h_pqr_report;
     int reported = -1;  // last step whose kernel has reported
     while (steps < kmax) {
       ++pqr_launched_;
-      const bool timed = H.kt.pick("pqr_step");
-      unsigned long long* stamp = timed ? H.kt.stamp(st) : nullptr;
-      if (timed) timed_steps_.push_back(steps);
+      // Timing (spaqr_time_kernel "pqr_step"): every launch is timed, in
+      // stretches of `every` consecutive launches bracketed by HIP events on
+      // this stream (two event packets per stretch, not per launch); the
+      // first launch of a stretch also stamps its own first start and last
+      // end on the GPU clock.
+      const bool timing = H.kt.on("pqr_step");
+      const bool opens = timing && run_left == 0;
+      unsigned long long* stamp = opens ? H.kt.stamp(st) : nullptr;
+      if (timing) timed_steps_.push_back(steps);
+      if (opens) {
+        H.kt.mark(st);
+        run_left = H.kt.every;
+        run_len = 0;
+      }
       launch_pqr_step<T>(dblk, total, total, states, parts, frop, dmap, active, steps, eps_, max_m, cw,
                          H.tune.pqr_reg_rows, stamp, H.d_pqr_report, tag, st);
+      if (timing) {
+        ++run_len;
+        if (--run_left == 0) H.kt.close(st, run_len);
+      }
       ++launches_;
       ++steps;
       if (steps >= kmax) break;
@@ -788,6 +804,7 @@ class Factorizer {
       wait_s_ += now_s() - t_spin;
       if (done) break;
     }
+    if (run_left > 0) H.kt.close(st, run_len);  // a stretch ends with its batch
     launch_pqr_finish<T>(d, (int)q.size(), states, steps, st);
     ++launches_;
     if (dbg) {
@@ -1947,7 +1964,7 @@ void apply_op_stream(Handle& H, bool transpose, double* x, double* stage, double
     if (transpose && b.n_nslots > 0)
       launch_apply_nsum(b.d_nslots, b.d_nptr, b.d_noff, b.n_nslots, stage, x, st);
     if (timed) {
-      H.kt.mark(st);
+      H.kt.close(st);
       H.kt.bytes += b.bytes;
       H.kt.flops += b.flops;
     }

@@ -54,6 +54,9 @@ struct KernelTimer {
   int64_t calls = 0, seen = 0;
   int every = 1;
   double seconds = 0.0, bytes = 0.0, flops = 0.0;
+  // in-kernel spans (first work-group start to last work-group end)
+  int64_t span_calls = 0;
+  double span_seconds = 0.0;
   // device stamps: STAMP_SLOTS x STAMP_STRIDE words per timed launch
   unsigned long long* d_stamp = nullptr;
   size_t stamp_cap = 0, stamp_used = 0;
@@ -62,6 +65,9 @@ struct KernelTimer {
   bool on(const char* f) const { return !family.empty() && family == f; }
   // true for the launches that are timed (every `every`-th one of the family)
   bool pick(const char* f) { return on(f) && (seen++ % every) == 0; }
+  // events come in pairs: mark() opens a timed stretch, close() ends it
+  // after the n launches it covered
+  std::vector<int> runs;
   void mark(hipStream_t s) {
     if (used == pool.size()) {
       hipEvent_t e;
@@ -69,6 +75,10 @@ struct KernelTimer {
       pool.push_back(e);
     }
     SPAQR_HIP(hipEventRecord(pool[used++], s));
+  }
+  void close(hipStream_t s, int n = 1) {
+    mark(s);
+    runs.push_back(n);
   }
 
   // Slot for the next timed launch.  Slots start at zero; a kernel folds
@@ -114,8 +124,8 @@ struct KernelTimer {
         t1 = std::max(t1, e[1]);
       }
       if (t0 != ~0ull && t1 >= t0) {
-        seconds += (double)(t1 - t0) / clock_hz;
-        ++calls;
+        span_seconds += (double)(t1 - t0) / clock_hz;
+        ++span_calls;
       }
     }
     SPAQR_HIP(hipMemsetAsync(d_stamp, 0, h.size() * sizeof(unsigned long long), stamp_stream));
@@ -128,20 +138,24 @@ struct KernelTimer {
       float ms = 0.f;
       SPAQR_HIP(hipEventElapsedTime(&ms, pool[i], pool[i + 1]));
       seconds += ms * 1e-3;
-      ++calls;
+      calls += i / 2 < runs.size() ? runs[i / 2] : 1;
     }
     used = 0;
+    runs.clear();
   }
   void reset(const char* f, int ev) {
     family = f ? f : "";
     every = ev > 0 ? ev : 1;
     used = 0;
+    runs.clear();
     if (d_stamp)
       SPAQR_HIP(hipMemset(d_stamp, 0, stamp_cap * STAMP_SLOTS * STAMP_STRIDE * sizeof(unsigned long long)));
     stamp_used = 0;
     calls = 0;
     seen = 0;
     seconds = bytes = flops = 0.0;
+    span_calls = 0;
+    span_seconds = 0.0;
   }
   ~KernelTimer() {
     for (auto e : pool) (void)hipEventDestroy(e);

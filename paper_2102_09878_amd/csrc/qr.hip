@@ -1075,7 +1075,7 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork&
       if (timed) kt->mark(s);
       SPAQR_HIP(hipLaunchCooperativeKernel((const void*)k_qrp_coop, dim3(nf * coop_segs), dim3(PBS), args, 0, s));
       if (timed) {
-        kt->mark(s);
+        kt->close(s);
         // algorithmic work of the panel: Householder QR of (m - j0) x kb,
         // the panel read and written once
         for (auto& d : h) {

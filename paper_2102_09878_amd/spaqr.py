@@ -51,7 +51,8 @@ class Stats(ctypes.Structure):
                 ("kernel_flops", ctypes.c_double),
                 ("level_interfaces", ctypes.c_int32 * MAX_LEVELS), ("level_aspect", ctypes.c_double * MAX_LEVELS),
                 ("level_cols", ctypes.c_int64 * MAX_LEVELS), ("level_rank1", ctypes.c_int64 * MAX_LEVELS),
-                ("level_rank2", ctypes.c_int64 * MAX_LEVELS), ("sync_wait_seconds", ctypes.c_double)]
+                ("level_rank2", ctypes.c_int64 * MAX_LEVELS), ("sync_wait_seconds", ctypes.c_double),
+                ("kernel_span_calls", ctypes.c_int64), ("kernel_span_seconds", ctypes.c_double)]
 
 
 class Tune(ctypes.Structure):
@@ -285,6 +286,7 @@ def spaqr_factor_stats(h):
                 device_bytes=s.device_bytes, flops=dict(zip(PHASES, s.flops)),
                 bytes=dict(zip(PHASES, s.bytes)), phase_seconds=dict(zip(PHASES, s.phase_seconds)),
                 factor_seconds=s.factor_seconds, sync_wait_seconds=s.sync_wait_seconds,
+                kernel_span_calls=s.kernel_span_calls, kernel_span_seconds=s.kernel_span_seconds,
                 kernel_calls=s.kernel_calls,
                 kernel_seconds=s.kernel_seconds, kernel_bytes=s.kernel_bytes, kernel_flops=s.kernel_flops,
                 levels_sparsified={m: dict(interfaces=s.level_interfaces[m], aspect=s.level_aspect[m],
