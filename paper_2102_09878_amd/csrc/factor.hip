@@ -1042,9 +1042,16 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
       gr.data = f.F + off + (int64_t)f.cs * f.ld;
       gr.ld = f.ld;
       gr.sl = f.s2;
+      // touch lists: only the clusters g did not hold yet (both lists sorted)
+      {
+        auto it = gr.clus.begin();
+        for (int c : f.nb) {
+          while (it != gr.clus.end() && *it < c) ++it;
+          if (it == gr.clus.end() || *it != c) touch[c].push_back(g);
+        }
+      }
       gr.clus = f.nb;
       gr.role = 0;
-      note(g);
       off += gr.nrows;
     }
     if (f.cN > 0 && f.rs > f.cs) {
@@ -1674,11 +1681,13 @@ void Factorizer<T>::merge(int m) {
     auto& cl = G[g].clus;
     bool hit = false;
     for (int& c : cl)
-      if (remap[c] >= 0) c = remap[c], hit = true;
+      if (remap[c] >= 0) {
+        c = remap[c], hit = true;
+        touch[c].push_back(g);  // the other clusters' lists hold g already
+      }
     if (!hit) continue;
     std::sort(cl.begin(), cl.end());
     cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
-    note(g);
   }
 }
 
