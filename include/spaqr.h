@@ -114,7 +114,7 @@ typedef struct {
 typedef struct {
   int32_t pqr_poll;        /* pivot steps launched ahead of the last one the GPU has reported (16)    */
   int32_t pqr_reg_rows;    /* tallest row window a pivot step keeps in registers, 0..1024 (1024)      */
-  int32_t tall_coop;       /* 1: tall FP32 panels in one cooperative launch; 0: two per column (1)   */
+  int32_t tall_coop;       /* 1: tall panels in one cooperative launch; 0: two launches per column (1)*/
   int32_t from_cache;      /* spaqr_autotune: 1 if the choice was read from the cache file           */
   int32_t evaluations;     /* settings timed when it was tuned                                        */
   int32_t pad_;
@@ -294,9 +294,9 @@ int spaqr_get_op(spaqr_handle h, int32_t i, spaqr_op_desc* desc, double* mat, in
 /* Project-written autotuner of the launch shapes for this handle's
  * problem (the batching form's tile choice): it times whole
  * factorizations with eps (the best of reps >= 1 runs per setting),
- * descends one knob at a time from the defaults (poll interval 4 / 16 /
- * 64 steps; register window 256 / 512 / 1024 rows; cooperative or
- * two-launch tall FP32 panels), keeps the fastest, and leaves the handle
+ * descends one knob at a time from the defaults (run-ahead window 4 / 8 /
+ * 16 steps; register window 256 / 512 / 1024 rows; cooperative or
+ * two-launch tall panels), keeps the fastest, and leaves the handle
  * factorized with it.  cache_path (may be NULL): a text file of
  * "signature poll rows coop t_default t_best evaluations" lines; an entry
  * whose signature (M, N, nnz, depth, skip, members, precision, eps, GPU

@@ -167,7 +167,7 @@ struct KernelTimer {
 struct TuneParams {
   int pqr_poll = 16;        // pivot steps launched ahead of the last step the GPU has reported
   int pqr_reg_rows = 1024;  // tallest 64-aligned window kept in registers by a pivot step
-  int tall_coop = 1;        // tall FP32 panels in one cooperative launch (else two launches per column)
+  int tall_coop = 1;        // tall panels in one cooperative launch (else two launches per column)
 };
 
 struct Handle {

@@ -384,16 +384,21 @@ __global__ __launch_bounds__(PBS) void k_qr_panel_reg(const QRDesc* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// panel of tall FP32 fronts, one cooperative launch per panel
+// panel of tall fronts, one cooperative launch per panel
 //
 // Work-group (f, s) holds rows j0 + s TSEG .. + TSEG of front f in registers
-// (same ownership as the register panel above).  Each column step needs two
+// (PR rows per thread: 4 in FP32, the ownership of the register panel above;
+// 2 in FP64, so a thread holds the same 128 registers of panel values).  Each column step needs two
 // sums over all row segments of the front - ||tail||^2 and the kb-1 dot
 // products - exchanged through small global buffers across two grid
 // barriers.  The step loop runs to the largest panel width of the launch in
 // every work-group, so all of them reach every barrier.
 // ---------------------------------------------------------------------------
-constexpr int TSEG = PBS * PRPT;
+template <typename T>
+struct CoopRows {
+  static constexpr int PR = sizeof(T) == 4 ? PRPT : PRPT / 2;
+  static constexpr int TSEG = PBS * PR;
+};
 
 struct CoopShared {
   double sh[8];
@@ -405,9 +410,9 @@ struct CoopShared {
   double Ts[NB][NB + 1];
 };
 
-template <int I>
-__device__ __forceinline__ void coop_step(float (&P)[PRPT][NB], int j0, int m, int kb, int rbase, int sg, int S,
-                                          float* tau, double* dpb, double* rowc_g, CoopShared& L) {
+template <typename T, int PR, int I>
+__device__ __forceinline__ void coop_step(T (&P)[PR][NB], int j0, int m, int kb, int rbase, int sg, int S,
+                                          T* tau, double* dpb, double* rowc_g, CoopShared& L) {
   namespace cg = cooperative_groups;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const bool work = I < kb;
@@ -421,17 +426,17 @@ __device__ __forceinline__ void coop_step(float (&P)[PRPT][NB], int j0, int m, i
   double* dp = dpb + (I & 1) * S * NB;
   if (work) {
     double part = 0.0;
-    float acc[NB - 1];
+    T acc[NB - 1];
 #pragma unroll
-    for (int q = 0; q < NB - 1; ++q) acc[q] = 0.0f;
+    for (int q = 0; q < NB - 1; ++q) acc[q] = T(0);
 #pragma unroll
-    for (int k = 0; k < PRPT; ++k) {
+    for (int k = 0; k < PR; ++k) {
       const int r = rbase + tid + PBS * k;
       if (r <= c || r >= m) continue;
-      const float xi = P[k][I];
+      const T xi = P[k][I];
       part += (double)xi * (double)xi;
 #pragma unroll
-      for (int q = 0; q < NB - 1; ++q) acc[q] = fmaf(xi, P[k][q < I ? q : q + 1], acc[q]);
+      for (int q = 0; q < NB - 1; ++q) acc[q] = fma(xi, P[k][q < I ? q : q + 1], acc[q]);
     }
     // row c lives in segment 0, thread I, slot 0
     if (sg == 0 && tid == I)
@@ -459,7 +464,7 @@ __device__ __forceinline__ void coop_step(float (&P)[PRPT][NB], int j0, int m, i
     __syncthreads();
     double beta, tv, scal;
     house_scalars(L.rowc[I], xn2, beta, tv, scal);
-    const double tvT = (double)static_cast<float>(tv);
+    const double tvT = (double)static_cast<T>(tv);
     if (tid < kb - 1) {
       double a = 0.0;
       for (int t = 0; t < S; ++t) a += dp[t * NB + tid];
@@ -478,64 +483,66 @@ __device__ __forceinline__ void coop_step(float (&P)[PRPT][NB], int j0, int m, i
       L.Ts[I][I] = tvT;
     }
 #pragma unroll
-    for (int k = 0; k < PRPT; ++k) {
+    for (int k = 0; k < PR; ++k) {
       const int r = rbase + tid + PBS * k;
       if (r < c || r >= m) continue;
       if (r == c) {
 #pragma unroll
         for (int q = I + 1; q < NB; ++q)
-          if (q < kb && tv != 0.0) P[k][q] = static_cast<float>((double)P[k][q] - L.fj[q]);
-        P[k][I] = static_cast<float>(beta);
+          if (q < kb && tv != 0.0) P[k][q] = static_cast<T>((double)P[k][q] - L.fj[q]);
+        P[k][I] = static_cast<T>(beta);
       } else if (tv != 0.0) {
-        P[k][I] = static_cast<float>(P[k][I] * scal);
+        P[k][I] = static_cast<T>(P[k][I] * scal);
         const double vi = P[k][I];
 #pragma unroll
         for (int q = I + 1; q < NB; ++q)
-          if (q < kb) P[k][q] = static_cast<float>((double)P[k][q] - L.fj[q] * vi);
+          if (q < kb) P[k][q] = static_cast<T>((double)P[k][q] - L.fj[q] * vi);
       }
     }
-    if (sg == 0 && tid == 0) tau[c] = static_cast<float>(tv);
+    if (sg == 0 && tid == 0) tau[c] = static_cast<T>(tv);
   }
   __syncthreads();
 }
 
 // kbmax is the same in every work-group, so every one runs the same steps
 // and reaches every grid barrier.
-template <int I>
-__device__ __forceinline__ void coop_steps(float (&P)[PRPT][NB], int j0, int m, int kb, int kbmax, int rbase, int sg,
-                                           int S, float* tau, double* dp, double* rowc_g, CoopShared& L) {
+template <typename T, int PR, int I>
+__device__ __forceinline__ void coop_steps(T (&P)[PR][NB], int j0, int m, int kb, int kbmax, int rbase, int sg,
+                                           int S, T* tau, double* dp, double* rowc_g, CoopShared& L) {
   if constexpr (I < NB) {
     if (I >= kbmax) return;
-    coop_step<I>(P, j0, m, kb, rbase, sg, S, tau, dp, rowc_g, L);
-    coop_steps<I + 1>(P, j0, m, kb, kbmax, rbase, sg, S, tau, dp, rowc_g, L);
+    coop_step<T, PR, I>(P, j0, m, kb, rbase, sg, S, tau, dp, rowc_g, L);
+    coop_steps<T, PR, I + 1>(P, j0, m, kb, kbmax, rbase, sg, S, tau, dp, rowc_g, L);
   }
 }
 
+template <typename T>
 __global__ __launch_bounds__(PBS) void k_qrp_coop(const QRDesc* __restrict__ D, int j0, int kbmax, int S,
                                                   QRWork ws) {
+  constexpr int PR = CoopRows<T>::PR;
   const int f = blockIdx.x / S, sg = blockIdx.x % S;
   const QRDesc d = D[f];
   const int kk = min(d.m, d.k);
   const int kb = j0 < kk ? min(NB, kk - j0) : 0;
-  float* A = static_cast<float*>(d.A);
+  T* A = static_cast<T*>(d.A);
   const int64_t lda = d.lda;
   const int m = d.m;
   const int tid = threadIdx.x;
-  const int rbase = j0 + sg * TSEG;
+  const int rbase = j0 + sg * CoopRows<T>::TSEG;
   __shared__ CoopShared L;
-  float P[PRPT][NB];
+  T P[PR][NB];
 #pragma unroll
-  for (int k = 0; k < PRPT; ++k) {
+  for (int k = 0; k < PR; ++k) {
     const int r = rbase + tid + PBS * k;
 #pragma unroll
-    for (int q = 0; q < NB; ++q) P[k][q] = (r < m && q < kb) ? A[r + (int64_t)(j0 + q) * lda] : 0.0f;
+    for (int q = 0; q < NB; ++q) P[k][q] = (r < m && q < kb) ? A[r + (int64_t)(j0 + q) * lda] : T(0);
   }
   for (int e = tid; e < NB * NB; e += PBS) L.Ts[e / NB][e % NB] = 0.0;
   __syncthreads();
-  coop_steps<0>(P, j0, m, kb, kbmax, rbase, sg, S, static_cast<float*>(d.tau), ws.dp + (int64_t)f * 2 * ws.MS * NB,
-                ws.gp + (int64_t)f * ws.MS * NB * NB, L);
+  coop_steps<T, PR, 0>(P, j0, m, kb, kbmax, rbase, sg, S, static_cast<T*>(d.tau),
+                       ws.dp + (int64_t)f * 2 * ws.MS * NB, ws.gp + (int64_t)f * ws.MS * NB * NB, L);
 #pragma unroll
-  for (int k = 0; k < PRPT; ++k) {
+  for (int k = 0; k < PR; ++k) {
     const int r = rbase + tid + PBS * k;
     if (r < m)
 #pragma unroll
@@ -1054,14 +1061,15 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork&
     // SPAQR_NO_COOP=1 keeps tall panels on the two-launches-per-column path
     // (for tools that cannot follow cooperative launches)
     static const bool no_coop = std::getenv("SPAQR_NO_COOP") != nullptr;
-    if (split && sizeof(T) == 4 && !no_coop && allow_coop) {
+    if (split && !no_coop && allow_coop) {
+      constexpr int TSEG = CoopRows<T>::TSEG;
       coop_segs = (mmax - j0 + TSEG - 1) / TSEG;
-      static int max_coop = -1;
+      static int max_coop = -1;  // per storage type
       if (max_coop < 0) {
         int per_cu = 0, dev = 0, cus = 0;
         SPAQR_HIP(hipGetDevice(&dev));
         SPAQR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        SPAQR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_qrp_coop, PBS, 0));
+        SPAQR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_qrp_coop<T>, PBS, 0));
         max_coop = per_cu * cus;
       }
       if ((int64_t)nf * coop_segs > max_coop || coop_segs > ws.MS) coop_segs = 0;
@@ -1073,7 +1081,7 @@ void launch_qr(const QRDesc* d_desc, const std::vector<QRDesc>& h, const QRWork&
       void* args[] = {(void*)&dd, (void*)&a_j0, (void*)&a_kb, (void*)&a_s, (void*)&a_ws};
       const bool timed = kt && kt->pick("qrp_coop");
       if (timed) kt->mark(s);
-      SPAQR_HIP(hipLaunchCooperativeKernel((const void*)k_qrp_coop, dim3(nf * coop_segs), dim3(PBS), args, 0, s));
+      SPAQR_HIP(hipLaunchCooperativeKernel((const void*)k_qrp_coop<T>, dim3(nf * coop_segs), dim3(PBS), args, 0, s));
       if (timed) {
         kt->close(s);
         // algorithmic work of the panel: Householder QR of (m - j0) x kb,

@@ -9,7 +9,7 @@
 //   * pqr_reg_rows  tallest 64-aligned row window a pivot step keeps in
 //                   registers (per-lane register tile of 2 to 16 rows, or
 //                   the memory path above it; both sum in the same order);
-//   * tall_coop     tall FP32 Householder panels in one cooperative launch
+//   * tall_coop     tall Householder panels in one cooperative launch
 //                   or in two launches per column.
 // The tuner times whole factorizations of the handle's own problem (the
 // best of `reps` runs per setting), descends one knob at a time from the
@@ -122,7 +122,7 @@ void autotune(Handle& H, double eps, int reps, const char* cache_path, spaqr_tun
       c.pqr_reg_rows = rr;
       consider(c);
     }
-    if (H.opt.precision == SPAQR_FP32_FACTOR) {
+    {
       TuneParams c = best;
       c.tall_coop = 1 - c.tall_coop;
       consider(c);

@@ -55,6 +55,31 @@ def test_split_tall_panels_fp32_match_oracle():
     s.close()
 
 
+@pytest.mark.parametrize("coop", [1, 0])
+def test_fp64_tall_panel_forms_match_oracle(coop):
+    """FP64 fronts over 1024 rows, with tall panels in one cooperative launch
+    (the default) or in two launches per column: with the oracle's ranks,
+    every op within 1e-10 of the oracle's, then x within 1e-8."""
+    p = grid_ls((34, 64), 34 * 64, 5)
+    f = osp.factorize(osp.analyze(p, 2), 1e-2, 1)
+    s = pk.Solver.from_problem(p, 2, 1, precision="fp64")
+    s.set_tune(tall_coop=coop)
+    s.factorize(1e-2, ranks=f.ranks)
+    assert s.stats()["num_ops"] == len(f.ops)
+    for i, o in enumerate(f.ops):
+        g = s.op(i)
+        ref = o[3] if o[0] == "elim" else o[2]
+        assert g["mat"].shape == ref.shape, i
+        if ref.size:
+            assert np.abs(g["mat"] - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max()), (i, o[0])
+    s.factorize(1e-2)
+    assert s.ranks() == f.ranks
+    xo, _ = osolve.cgls(osolve.Operator(f), p.b, tol=1e-12)
+    x, info = s.cgls(dev(p.b), tol=1e-12)
+    assert info["converged"] and np.linalg.norm(x.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
+    s.close()
+
+
 def test_autotune_caches_and_reloads(tmp_path):
     c = CONFIGS[1]
     p = config_problem(1)
