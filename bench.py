@@ -458,6 +458,9 @@ def main() -> int:
                                            f"stream around stretches of {args.every} consecutive launches"),
                     "in_kernel_span_us": (kern["span_seconds"] / kern["span_calls"] * 1e6
                                           if kern["span_calls"] else None),
+                    "rocprof_avg_us": cnt.get("rocprof_avg_us") if cnt else None,
+                    "rocprof_note": ("rocprofv3 --kernel-trace average of k_pqr_step over the 256x256 FP32 step "
+                                     "(profiles/pmc_k_pqr_step.json, same pqr.hip)"),
                     "algorithmic_flops_per_launch": kern["flops"] / kern["calls"],
                     "algorithmic_bytes_per_launch": per_launch,
                     "intensity_flop_per_byte": kern["flops"] / kern["bytes"] if kern["bytes"] else None,
