@@ -104,7 +104,7 @@ print(json.dumps(dict(seconds=dt, flops=sum(v[0] for v in f.ledger.values()), it
                        f"{target_flops:.3e} flops of the 256x256 job" + full)}
 
 
-def _batch_form(steps: int, warmup: int) -> dict:
+def _batch_form(steps: int, warmup: int, tune_shapes: bool = True) -> dict:
     """64 independent grids (side 48..160, M = 2N, eps 1e-2, FP32 factor) in
     one batch handle: factorize + per-problem CGLS to 1e-10 per step."""
     import numpy as np
@@ -118,7 +118,7 @@ def _batch_form(steps: int, warmup: int) -> dict:
     t = time.perf_counter()
     bs = pk.BatchSolver.from_problems(probs, [p.meta["depth"] for p in probs], skip=2, precision="fp32")
     t_an = time.perf_counter() - t
-    tune = bs.autotune(1e-2, reps=1, cache_path=TUNE_CACHE)
+    tune = bs.autotune(1e-2, reps=1, cache_path=TUNE_CACHE) if tune_shapes else None
     b = torch.as_tensor(np.concatenate([p.b for p in probs]), device="cuda")
     for _ in range(warmup):
         bs.factorize(1e-2)
@@ -327,6 +327,8 @@ def main() -> int:
                     help="launches of the roofline kernel per HIP-event-timed stretch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch form")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="run only the 64-problem batch form and print its measurements (a profiling aid)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (calibrates HBM traffic counters)")
@@ -340,6 +342,9 @@ def main() -> int:
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}))
+        return 0
+    if args.only_batch:
+        print(json.dumps({"batch_form": _batch_form(args.steps, args.warmup, not args.no_tune)}))
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this "
@@ -433,7 +438,7 @@ def main() -> int:
     if "fp32" in xs and "fp64" in xs:
         forms["fp32"]["x_err_vs_fp64_form"] = float(np.linalg.norm(xs["fp32"] - xs["fp64"]) /
                                                     np.linalg.norm(xs["fp64"]))
-    batch = None if args.no_batch else _batch_form(args.steps, args.warmup)
+    batch = None if args.no_batch else _batch_form(args.steps, args.warmup, not args.no_tune)
     extra_steps = min(args.steps, 2)
     square = None if args.no_batch else _square_form(extra_steps, args.warmup)
     invpoi = None if args.no_batch else _inverse_poisson_form(extra_steps, args.warmup)
