@@ -204,6 +204,9 @@ enum Phase { PH_ELIM = 0, PH_REASSIGN = 1, PH_SCALE = 2, PH_SPARSIFY = 3, PH_MER
 // from it (and rows or columns kept because of it) would differ from run to
 // run and from any other implementation.
 constexpr double kNoiseRank = 1000.0;
+// batches of at least this many matrices read a matrix's state before its
+// columns in a pivot step (see k_pqr_step)
+constexpr int kCheckFirstMats = 2;
 template <typename T>
 constexpr double unit_roundoff() {
   return sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
@@ -748,6 +751,8 @@ class Factorizer {
     // read through the stream instead.
     const unsigned tag = (++H.pqr_tag) & 0xFFFFFFu;
     int run_left = 0, run_len = 0;  // timed stretch in progress
+    // batches of several matrices skip the fetches of the ones that stopped
+    const bool check_first = live_m >= kCheckFirstMats;
     volatile unsigned long long* rep = H.h_pqr_report;
     int reported = -1;  // last step whose kernel has reported
     while (steps < kmax) {
@@ -767,7 +772,7 @@ class Factorizer {
         run_len = 0;
       }
       launch_pqr_step<T>(dblk, total, total, states, parts, frop, dmap, active, steps, eps_, max_m, cw,
-                         H.tune.pqr_reg_rows, stamp, H.d_pqr_report, tag, st);
+                         H.tune.pqr_reg_rows, stamp, H.d_pqr_report, tag, check_first, st);
       if (timing) {
         ++run_len;
         if (--run_left == 0) H.kt.close(st, run_len);

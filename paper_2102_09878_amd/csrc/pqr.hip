@@ -162,7 +162,11 @@ struct StampScope {
   }
 };
 
-template <typename T, int PQ, int NC>
+// CF: the work-group reads its matrix's state before fetching anything else
+// and does nothing more once that matrix has stopped (batches of many
+// matrices, whose ranks differ); without it every fetch is issued at once
+// (one round trip less per step, for the chains of single matrices).
+template <typename T, int PQ, int NC, bool CF>
 __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, PQRState* __restrict__ S,
                                                  PQRPart* __restrict__ parts, int total_parts,
                                                  const double* __restrict__ frop,
@@ -202,12 +206,13 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
   double* vn1 = d.work;
   double* vn2 = d.work + n;
   double* done = d.work + 2 * n;
+  const bool idle = CF && sp.stopped;
   double pval[PL];
   int pidx[PL];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
     const int k = tid + u * BS;
-    if (k < d.nblk) {
+    if (!idle && k < d.nblk) {
       const PQRPart q = prd[d.blk0 + k];
       pval[u] = q.val, pidx[u] = q.idx;
     } else {
@@ -216,7 +221,7 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
   }
   // squared Frobenius norm (first step only): thread t sums chunks t, t + BS, ...
   double fro = 0.0;
-  if (i == 0)
+  if (i == 0 && !idle)
     for (int k = tid; k < d.nblk; k += BS) fro += frop[d.blk0 + k];
   // Register rows form a 64-aligned window: lane l holds rows i0 + l + 64 q,
   // so every per-lane partial sum runs over the rows congruent to l mod 64
@@ -231,7 +236,7 @@ __global__ __launch_bounds__(BS) void k_pqr_step(const PQRDesc* __restrict__ D, 
   double v1p[NC], v2p[NC], dnp[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) v1p[k] = 0.0, v2p[k] = 1.0, dnp[k] = 1.0;
-  if (regs) {
+  if (regs && !idle) {
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       const int j = jcol[k] < c1 ? jcol[k] : c0;
@@ -881,16 +886,22 @@ template <typename T>
 void launch_pqr_step(const PQRDesc* d_blk, int nblocks, int total_parts, PQRState* states,
                      PQRPart* parts, const double* frop, const int2* bmap, int* active, int i, double eps,
                      int max_m, int cw, int reg_rows, unsigned long long* stamp, unsigned long long* report,
-                     unsigned tag, hipStream_t s) {
+                     unsigned tag, bool check_first, hipStream_t s) {
   if (nblocks <= 0) return;
   if (i >= (1 << 20)) throw Error(SPAQR_EARG, "internal: pivot step index beyond the progress word");
   const size_t lds = (size_t)std::max(1, max_m) * sizeof(double);
   if (lds > 64 * 1024) throw Error(SPAQR_EARG, "rank-revealing QR block taller than 8192 rows");
   const int rows = max_m - (i & ~63);
   const bool regs = rows <= std::min(reg_rows, 1024);
-#define SPAQR_PQR_GO(Q, C)                                                                                   \
-  hipLaunchKernelGGL((k_pqr_step<T, Q, C>), dim3(nblocks), dim3(BS), lds, s, d_blk, states, parts, total_parts,  \
-                     frop, bmap, active, i, eps, stamp, report, tag)
+#define SPAQR_PQR_GO(Q, C)                                                                                    \
+  do {                                                                                                          \
+    if (check_first)                                                                                            \
+      hipLaunchKernelGGL((k_pqr_step<T, Q, C, true>), dim3(nblocks), dim3(BS), lds, s, d_blk, states, parts,    \
+                         total_parts, frop, bmap, active, i, eps, stamp, report, tag);                          \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_pqr_step<T, Q, C, false>), dim3(nblocks), dim3(BS), lds, s, d_blk, states, parts,   \
+                         total_parts, frop, bmap, active, i, eps, stamp, report, tag);                          \
+  } while (0)
   if (cw == PQR_CW) {
     if (!regs)
       SPAQR_PQR_GO(0, PQR_CW / 4);
@@ -1019,7 +1030,7 @@ void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int st
   template void launch_pqr_init<T>(const PQRDesc*, int, PQRState*, PQRPart*, double*, const int2*, hipStream_t); \
   template void launch_pqr_step<T>(const PQRDesc*, int, int, PQRState*, PQRPart*, const double*, const int2*,  \
                                    int*, int, double, int, int, int, unsigned long long*,                     \
-                                   unsigned long long*, unsigned, hipStream_t);                               \
+                                   unsigned long long*, unsigned, bool, hipStream_t);                         \
   template void launch_pqr_finish<T>(const PQRDesc*, int, PQRState*, int, hipStream_t);                   \
   template int pqr_run_width<T>(int, const std::vector<int>&, int*);                                     \
   template void launch_pqr_run<T>(const PQRDesc*, int, const int2*, const PQRXch&, double, int,            \

@@ -356,7 +356,7 @@ template <typename T>
 void launch_pqr_step(const PQRDesc* d_blk, int nblocks, int total_parts, PQRState* states,
                      PQRPart* parts, const double* frop, const int2* bmap, int* active, int i, double eps,
                      int max_m, int cw, int reg_rows, unsigned long long* stamp, unsigned long long* report,
-                     unsigned tag, hipStream_t s);
+                     unsigned tag, bool check_first, hipStream_t s);
 template <typename T>
 void launch_pqr_finish(const PQRDesc* d_desc, int nmat, PQRState* states, int steps, hipStream_t s);
 // Persistent form: all pivot steps of a batch in one cooperative launch of
