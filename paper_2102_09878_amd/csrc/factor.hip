@@ -221,12 +221,6 @@ class Factorizer {
   void run();
 
  private:
-  // Column slots of a group's data: the slots of the clusters it was built
-  // from, one block after the other, with each block's (cluster, begin, end).
-  struct SlotList {
-    std::vector<int> v;
-    std::vector<std::array<int, 3>> blk;
-  };
   typedef std::shared_ptr<const SlotList> Slots;
   // the list `cols` made of the slot lists of `head` (if >= 0) then of the
   // clusters `cl`, in that order (the blocks are cut by their sizes)
@@ -866,19 +860,25 @@ void Factorizer<T>::init_groups() {
   SPAQR_HIP(hipMemsetAsync(base, 0, std::max<int64_t>(1, P.init_elems) * sizeof(T), st));
   launch_scatter_csr<T>(base, H.d_init_dst, H.d_ahat, P.nnz, st);
   launches_ += 2;
-  for (const InitGroup& ig : P.init_groups) {
+  const bool built = H.init_slots.size() == P.init_groups.size();
+  if (!built) H.init_slots.assign(P.init_groups.size(), nullptr);
+  for (size_t k = 0; k < P.init_groups.size(); ++k) {
+    const InitGroup& ig = P.init_groups[k];
     RG g;
     g.owner = ig.owner;
     g.data = base + ig.offset;
     g.ld = ig.ld;
     g.nrows = (int)ig.rows.size();
-    auto L = std::make_shared<SlotList>();
-    for (int c : ig.clus) {
-      const auto& cells = P.clusters[c].cells;
-      L->blk.push_back({c, (int)L->v.size(), (int)(L->v.size() + cells.size())});
-      L->v.insert(L->v.end(), cells.begin(), cells.end());
+    if (!built) {
+      auto L = std::make_shared<SlotList>();
+      for (int c : ig.clus) {
+        const auto& cells = P.clusters[c].cells;
+        L->blk.push_back({c, (int)L->v.size(), (int)(L->v.size() + cells.size())});
+        L->v.insert(L->v.end(), cells.begin(), cells.end());
+      }
+      H.init_slots[k] = L;
     }
-    g.sl = L;
+    g.sl = H.init_slots[k];
     g.clus = ig.clus;
     C[ig.owner].groups.push_back((int)G.size());
     G.push_back(std::move(g));

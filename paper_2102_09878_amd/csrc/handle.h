@@ -3,6 +3,8 @@
 #pragma once
 
 #include <algorithm>
+#include <array>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -170,6 +172,15 @@ struct TuneParams {
   int tall_coop = 1;        // tall panels in one cooperative launch (else two launches per column)
 };
 
+// Column slots of a group's data: the slots of the clusters it was built
+// from, one block after the other, with each block's (cluster, begin, end).
+// Immutable once built and shared between groups (and, for the initial
+// groups, between factorizations).
+struct SlotList {
+  std::vector<int> v;
+  std::vector<std::array<int, 3>> blk;
+};
+
 struct Handle {
   std::string err;
   TuneParams tune;
@@ -232,6 +243,9 @@ struct Handle {
   unsigned long long* h_pqr_report = nullptr;
   unsigned long long* d_pqr_report = nullptr;
   unsigned pqr_tag = 0;
+  // slot lists of the initial groups (structural: built by the first
+  // factorization, reused by the next ones)
+  std::vector<std::shared_ptr<const SlotList>> init_slots;
 
   ~Handle();
   void ensure_device();
