@@ -420,6 +420,17 @@ class Factorizer {
   }
   double wait_s_ = 0.0;
   int report_fallbacks_ = 0;  // pivot-step loops that fell back to a stream read
+  // how long the pivot-step loop waits for the report word to advance before
+  // reading the live count through the stream: 20 ms, or
+  // SPAQR_PQR_REPORT_WAIT_MS (0 takes the stream read at every wait; tests
+  // use it to run that path)
+  static double report_wait_s() {
+    static const double w = [] {
+      const char* e = std::getenv("SPAQR_PQR_REPORT_WAIT_MS");
+      return e ? std::max(0.0, std::atof(e)) * 1e-3 : 0.02;
+    }();
+    return w;
+  }
 
   int next_forced() {
     if (!forced_) return -1;
@@ -791,9 +802,10 @@ class Factorizer {
         const double t = now_s();
         if (t_wait < 0.0) {
           t_wait = t;
-        } else if (t - t_wait > 0.02) {
+        } else if (t - t_wait > report_wait_s()) {
           SPAQR_HIP(hipMemcpyAsync(h_active, active, sizeof(int), hipMemcpyDeviceToHost, st));
-          sync();
+          SPAQR_HIP(hipStreamSynchronize(st));  // counted in the spin's wait below
+          ++syncs_;
           ++report_fallbacks_;
           done = *h_active == 0;
           reported = steps - 1;
