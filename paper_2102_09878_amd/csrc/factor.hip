@@ -216,7 +216,7 @@ template <typename T>
 class Factorizer {
  public:
   Factorizer(Handle& h, double eps, const int* forced, int nforced)
-      : H(h), P(h.P), st(h.stream), eps_(eps), forced_(forced), nforced_(nforced) {}
+      : H(h), P(h.P), raw_st_(h.stream), eps_(eps), forced_(forced), nforced_(nforced) {}
 
   void run();
 
@@ -267,7 +267,19 @@ class Factorizer {
 
   Handle& H;
   Plan& P;
-  hipStream_t st;
+  // The library's stream.  Converting `st` to hipStream_t first issues the
+  // descriptor uploads still pending (upload() below defers and merges
+  // them), so every operation enqueued through it runs after its
+  // descriptors have been copied.
+  struct Stream {
+    Factorizer* f;
+    operator hipStream_t() const {
+      f->flush_uploads();
+      return f->raw_st_;
+    }
+  };
+  hipStream_t raw_st_;
+  Stream st{this};
   double eps_;
   const int* forced_;
   int nforced_;
@@ -286,15 +298,37 @@ class Factorizer {
   static int64_t pad(int64_t m) { return std::max<int64_t>(8, (m + 7) / 8 * 8); }
   static bool has(const std::vector<int>& v, int c) { return std::binary_search(v.begin(), v.end(), c); }
 
+  // Descriptor upload through pinned staging memory.  The copy is not
+  // issued at once: uploads that follow each other in both the staging
+  // and the device arena (same 256-byte rounding in both) are merged into
+  // one pending copy, issued when anything is next enqueued on `st`.  A
+  // pointer returned here must therefore only be handed to work enqueued
+  // in a later statement (never in the same argument list as `st`, whose
+  // conversion may be evaluated first).
+  char* pend_h_ = nullptr;
+  char* pend_d_ = nullptr;
+  size_t pend_n_ = 0;
+  void flush_uploads() {
+    if (pend_n_ == 0) return;
+    const size_t n = pend_n_;
+    pend_n_ = 0;
+    SPAQR_HIP(hipMemcpyAsync(pend_d_, pend_h_, n, hipMemcpyHostToDevice, raw_st_));
+  }
   template <class D>
   D* upload(const std::vector<D>& v) {
     if (v.empty()) return nullptr;
     const size_t b = v.size() * sizeof(D);
-    void* hp = H.stage.alloc(b);
+    const size_t br = (b + 255) & ~size_t(255);
+    char* hp = static_cast<char*>(H.stage.alloc(br));
     std::memcpy(hp, v.data(), b);
-    void* dp = H.arena.alloc(b);
-    SPAQR_HIP(hipMemcpyAsync(dp, hp, b, hipMemcpyHostToDevice, st));
-    return static_cast<D*>(dp);
+    char* dp = static_cast<char*>(H.arena.alloc(br));
+    if (pend_n_ > 0 && hp == pend_h_ + pend_n_ && dp == pend_d_ + pend_n_) {
+      pend_n_ += br;
+    } else {
+      flush_uploads();
+      pend_h_ = hp, pend_d_ = dp, pend_n_ = br;
+    }
+    return reinterpret_cast<D*>(dp);
   }
 
   // int pool: colmaps etc. collected per launch, uploaded once
@@ -363,7 +397,8 @@ class Factorizer {
       fm.xd[k].out = dense + off;
       off += fm.xd[k].n;
     }
-    launch_expand_maps(upload(fm.xd), (int)fm.xd.size(), st);
+    const ExpandDesc* dxd = upload(fm.xd);
+    launch_expand_maps(dxd, (int)fm.xd.size(), st);
     ++launches_;
     return dense;
   }
@@ -730,10 +765,10 @@ class Factorizer {
     qb.reserve(bmap.size());
     for (const int2& b : bmap) qb.push_back(q[b.x]);
     const PQRDesc* dblk = upload(qb);
+    int* active = upload(std::vector<int>{live_m});
     auto* states = static_cast<PQRState*>(H.arena.alloc(2 * q.size() * sizeof(PQRState)));
     auto* parts = static_cast<PQRPart*>(H.arena.alloc(2 * (size_t)total * sizeof(PQRPart)));
     auto* frop = static_cast<double*>(H.arena.alloc((size_t)total * sizeof(double)));
-    int* active = upload(std::vector<int>{live_m});
     int* h_active = static_cast<int*>(H.stage.alloc(sizeof(int)));
     static const bool dbg = std::getenv("SPAQR_DEBUG_PQR") != nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1039,7 +1074,8 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
   }
   int* dmaps = expand(fm);
   for (size_t i = 0; i < gd.size(); ++i) gd[i].colmap = dmaps + gd_map[i];
-  launch_gather<T>(upload(gd), (int)gd.size(), maxc, st);
+  const GatherDesc* dgd = upload(gd);
+  launch_gather<T>(dgd, (int)gd.size(), maxc, st);
   ++launches_;
   for (auto& f : fr) dump_front("elim", f.s, f.F, f.ld, f.m, f.n, f.cols);
   run_qr(qd);
@@ -1137,7 +1173,8 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
   }
   int od_rows = 0;
   for (const OwnerDesc& o : od) od_rows = std::max(od_rows, o.nrows);
-  launch_owner<T>(upload(od), (int)od.size(), od_rows, st);
+  const OwnerDesc* dod = upload(od);
+  launch_owner<T>(dod, (int)od.size(), od_rows, st);
   ++launches_;
   int* h_owner = static_cast<int*>(H.stage.alloc((std::max<size_t>(1, nown) + qe.size()) * sizeof(int)));
   int* h_rank = h_owner + std::max<size_t>(1, nown);
@@ -1189,7 +1226,8 @@ void Factorizer<T>::eliminate_round(const std::vector<int>& sel) {
   }
   int* drp = upload(rp.v);
   for (size_t i = 0; i < rd.size(); ++i) rd[i].rows = drp + rd_rows[i];
-  launch_rowcopy<T>(upload(rd), (int)rd.size(), maxcols, st);
+  const RowCopyDesc* drd = upload(rd);
+  launch_rowcopy<T>(drd, (int)rd.size(), maxcols, st);
   ++launches_;
   timer_end();
 }
@@ -1277,11 +1315,13 @@ void Factorizer<T>::scale_all() {
   }
   int* dmaps = expand(fm);
   for (size_t i = 0; i < gd.size(); ++i) gd[i].colmap = dmaps + gd_map[i];
-  launch_gather<T>(upload(gd), (int)gd.size(), maxc, st);
+  const GatherDesc* dgd = upload(gd);
+  launch_gather<T>(dgd, (int)gd.size(), maxc, st);
   ++launches_;
   for (auto& f : sf) dump_front("scale", f.p, f.F, f.ld, f.m, f.n, f.cols);
   run_qr(qd);
-  launch_extract<T>(upload(ed), (int)ed.size(), st);
+  const ExtractDesc* ded = upload(ed);
+  launch_extract<T>(ded, (int)ed.size(), st);
   ++launches_;
   for (auto& f : sf) {
     record_op(1, PH_SCALE, Rpp[f.p], nullptr, f.cs, f.cs, 0, C[f.p].slots, {});
@@ -1344,7 +1384,9 @@ void Factorizer<T>::scale_all() {
   std::vector<int2> trb;
   for (size_t i = 0; i < td.size(); ++i)
     for (int b = 0; b * TRSM_ROWS < td[i].nrows; ++b) trb.push_back(make_int2((int)i, b));
-  launch_trsm<T>(upload(td), (int)td.size(), td_rows, td_c, upload(trb), (int)trb.size(), st);
+  const TrsmDesc* dtd = upload(td);
+  const int2* dtrb = upload(trb);
+  launch_trsm<T>(dtd, (int)td.size(), td_rows, td_c, dtrb, (int)trb.size(), st);
   ++launches_;
   timer_end();
   // median aspect ratio of the scaled diagonal blocks (Section 4.2)
@@ -1548,10 +1590,12 @@ void Factorizer<T>::step2_round(const std::vector<int>& sel) {
   int* dpool = upload(pool.v);
   for (size_t i = 0; i < gd.size(); ++i) gd[i].colmap = dpool + gd_map[i];
   for (size_t i = 0; i < sd.size(); ++i) sd[i].colmap = dpool + sd_map[i];
-  launch_gather<T>(upload(gd), (int)gd.size(), maxc, st);
+  const GatherDesc* dgd = upload(gd);
+  launch_gather<T>(dgd, (int)gd.size(), maxc, st);
   log_shapes("step2", pd);
   run_pqr(pd);
-  launch_scatter<T>(upload(sd), (int)sd.size(), st);
+  const ScatterDesc* dsd = upload(sd);
+  launch_scatter<T>(dsd, (int)sd.size(), st);
   launches_ += 2;
   int* h = static_cast<int*>(H.stage.alloc(std::max<size_t>(1, sel.size()) * sizeof(int)));
   SPAQR_HIP(hipMemcpyAsync(h, d_rank, sel.size() * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1624,7 +1668,8 @@ void Factorizer<T>::reassign_group_rows(int gi) {
   d.lda = src.ld;
   d.nrows = src.nrows;
   d.ncl = (int)src.clus.size();
-  launch_owner<T>(upload(std::vector<OwnerDesc>{d}), 1, d.nrows, st);
+  const OwnerDesc* dod = upload(std::vector<OwnerDesc>{d});
+  launch_owner<T>(dod, 1, d.nrows, st);
   int* h = static_cast<int*>(H.stage.alloc(src.nrows * sizeof(int)));
   SPAQR_HIP(hipMemcpyAsync(h, d_owner, src.nrows * sizeof(int), hipMemcpyDeviceToHost, st));
   sync();
@@ -1657,7 +1702,8 @@ void Factorizer<T>::reassign_group_rows(int gi) {
   }
   int* drp = upload(rp.v);
   for (size_t i = 0; i < rd.size(); ++i) rd[i].rows = drp + rmap[i];
-  launch_rowcopy<T>(upload(rd), (int)rd.size(), (int)src.slots().size(), st);
+  const RowCopyDesc* drd = upload(rd);
+  launch_rowcopy<T>(drd, (int)rd.size(), (int)src.slots().size(), st);
   launches_ += 2;
 }
 
