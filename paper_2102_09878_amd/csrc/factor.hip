@@ -1384,6 +1384,20 @@ void Factorizer<T>::scale_all() {
   std::vector<int2> trb;
   for (size_t i = 0; i < td.size(); ++i)
     for (int b = 0; b * TRSM_ROWS < td[i].nrows; ++b) trb.push_back(make_int2((int)i, b));
+  {
+    static const bool on = std::getenv("SPAQR_DEBUG_SHAPES") != nullptr;
+    if (on) {
+      double work = 0.0, wmax = 0.0;
+      int64_t rb = 0;
+      for (const TrsmDesc& d : td) {
+        rb += (d.nrows + TRSM_ROWS - 1) / TRSM_ROWS;
+        work += (double)d.nrows * d.c * d.c;
+        wmax = std::max(wmax, (double)d.c * d.c);
+      }
+      std::fprintf(stderr, "[spaqr] L%d trsm count %zu rowblocks %lld max_rows %d max_c %d sum_rc2 %.3e max_c2 %.3e\n",
+                   level_, td.size(), (long long)rb, td_rows, td_c, work, wmax);
+    }
+  }
   const TrsmDesc* dtd = upload(td);
   const int2* dtrb = upload(trb);
   launch_trsm<T>(dtd, (int)td.size(), td_rows, td_c, dtrb, (int)trb.size(), st);
