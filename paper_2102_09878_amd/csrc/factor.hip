@@ -858,8 +858,17 @@ class Factorizer {
       SPAQR_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       SPAQR_HIP(hipEventElapsedTime(&ms, e0, e1));
-      std::fprintf(stderr, "[pqr_steps] L%d r%d nmat %zu G %d cw %d max_m %d steps %d  %.1f us  %.2f us/step\n",
-                   level_, round_, q.size(), total, cw, max_m, steps, ms * 1e3, ms * 1e3 / std::max(1, steps));
+      // share of the launched work-group steps that belonged to a live matrix
+      double live_wg = 0.0;
+      for (const PQRDesc& e : q) {
+        int r = 0;
+        if (e.rank_out) SPAQR_HIP(hipMemcpy(&r, e.rank_out, sizeof(int), hipMemcpyDeviceToHost));
+        live_wg += (double)e.nblk * std::min(r + 1, steps);
+      }
+      std::fprintf(stderr,
+                   "[pqr_steps] L%d r%d nmat %zu G %d cw %d max_m %d steps %d  %.1f us  %.2f us/step  live %.3f\n",
+                   level_, round_, q.size(), total, cw, max_m, steps, ms * 1e3, ms * 1e3 / std::max(1, steps),
+                   live_wg / std::max(1.0, (double)total * steps));
       SPAQR_HIP(hipEventDestroy(e0));
       SPAQR_HIP(hipEventDestroy(e1));
     }
