@@ -748,17 +748,32 @@ class Factorizer {
     // 8-column chunks: wider ones (fewer partials to scan, more columns per
     // wave) measured slower at every matrix height here
     const int cw = PQR_CW;
-    std::vector<int2> bmap;
     for (size_t k = 0; k < q.size(); ++k) {
       q[k].cw = cw;
       q[k].blk0 = total;
       q[k].nblk = std::max(1, (q[k].n + cw - 1) / cw);
-      for (int c = 0; c < q[k].nblk; ++c) bmap.push_back(make_int2((int)k, c));
       total += q[k].nblk;
       kmax = std::max(kmax, std::min(q[k].m, q[k].n));
       max_m = std::max(max_m, q[k].m);
       if (std::min(q[k].m, q[k].n) > 0) ++live_m;
     }
+    // Work-groups listed matrix by matrix in decreasing order of min(m, n),
+    // the most steps a matrix can take: a matrix has stopped by the end of
+    // step min(m, n) (exhausted, if nothing stopped it before) and has copied
+    // its final state to both state slots by the end of the step after, so
+    // step i launches only the prefix of matrices with min(m, n) >= i - 1.
+    // The list order changes nothing computed: each work-group finds its
+    // matrix and chunk in the list, and partials keep their per-matrix place.
+    std::vector<int> order(q.size());
+    for (size_t k = 0; k < q.size(); ++k) order[k] = (int)k;
+    auto steps_of = [&](int k) { return std::min(q[k].m, q[k].n); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return steps_of(a) > steps_of(b); });
+    std::vector<int2> bmap;
+    for (int k : order)
+      for (int c = 0; c < q[k].nblk; ++c) bmap.push_back(make_int2(k, c));
+    size_t pre_k = 0;  // matrices in the launched prefix for the current step
+    int pre_g = 0;     // and their work-groups
+    double launched_wg = 0.0;
     const PQRDesc* d = upload(q);
     const int2* dmap = upload(bmap);
     std::vector<PQRDesc> qb;
@@ -811,7 +826,13 @@ class Factorizer {
         run_left = H.kt.every;
         run_len = 0;
       }
-      launch_pqr_step<T>(dblk, total, total, states, parts, frop, dmap, active, steps, eps_, max_m, cw,
+      if (steps == 0 || steps_of(order[pre_k - 1]) < steps - 1) {
+        // (re)form the prefix: every matrix that can still be running
+        pre_k = 0, pre_g = 0;
+        while (pre_k < order.size() && steps_of(order[pre_k]) >= steps - 1) pre_g += q[order[pre_k++]].nblk;
+      }
+      launched_wg += pre_g;
+      launch_pqr_step<T>(dblk, pre_g, total, states, parts, frop, dmap, active, steps, eps_, max_m, cw,
                          H.tune.pqr_reg_rows, stamp, H.d_pqr_report, tag, check_first, st);
       if (timing) {
         ++run_len;
@@ -866,9 +887,10 @@ class Factorizer {
         live_wg += (double)e.nblk * std::min(r + 1, steps);
       }
       std::fprintf(stderr,
-                   "[pqr_steps] L%d r%d nmat %zu G %d cw %d max_m %d steps %d  %.1f us  %.2f us/step  live %.3f\n",
+                   "[pqr_steps] L%d r%d nmat %zu G %d cw %d max_m %d steps %d  %.1f us  %.2f us/step  live %.3f"
+                   "  launched %.3f\n",
                    level_, round_, q.size(), total, cw, max_m, steps, ms * 1e3, ms * 1e3 / std::max(1, steps),
-                   live_wg / std::max(1.0, (double)total * steps));
+                   live_wg / std::max(1.0, (double)total * steps), launched_wg / std::max(1.0, (double)total * steps));
       SPAQR_HIP(hipEventDestroy(e0));
       SPAQR_HIP(hipEventDestroy(e1));
     }
