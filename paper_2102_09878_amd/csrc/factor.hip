@@ -804,7 +804,8 @@ class Factorizer {
     // find every matrix stopped and only carry the state over.  Should the
     // report not advance for a long time (more than 20 ms), the count is
     // read through the stream instead.
-    const unsigned tag = (++H.pqr_tag) & 0xFFFFFFu;
+    unsigned tag = (++H.pqr_tag) & 0xFFFFFFu;
+    if (tag == 0) tag = (++H.pqr_tag) & 0xFFFFFFu;  // 0 is what an unwritten report word holds
     int run_left = 0, run_len = 0;  // timed stretch in progress
     // batches of several matrices skip the fetches of the ones that stopped
     const bool check_first = live_m >= kCheckFirstMats;
